@@ -156,18 +156,27 @@ def transform_matrix(n: int, bc: int, dtype=np.float64) -> np.ndarray:
 
     wall:     M[q, i] = cos(pi q (i + 1/2) / n)               (DCT-II)
     periodic: half-complex real DFT, M[q, i] = cos(2 pi q i / n) for q <= n/2,
-              M[n-m, i] = -sin(2 pi m i / n) for 0 < m < n/2 (Im of the DFT)."""
-    i = np.arange(n, dtype=dtype)
+              M[n-m, i] = -sin(2 pi m i / n) for 0 < m < n/2 (Im of the DFT).
+
+    The angles are multiples of pi/(2n); the integer multiple is reduced
+    modulo one period exactly (integer arithmetic) before the cosine is
+    taken, so each entry is accurate to rounding even when q*i is large."""
+    i = np.arange(n, dtype=np.int64)
     M = np.empty((n, n), dtype=dtype)
     pi = dtype(np.pi) if dtype is not np.longdouble else np.longdouble("3.14159265358979323846264338327950288")
     if bc == WALL:
+        # pi q (2i+1) / (2n): multiple r = q (2i+1) of pi/(2n), period 4n
         for q in range(n):
-            M[q] = np.cos(pi * q * (i + dtype(0.5)) / n)
+            r = (q * (2 * i + 1)) % (4 * n)
+            M[q] = np.cos(pi * r.astype(dtype) / (2 * n))
     else:
+        # 2 pi q i / n: multiple r = q i of 2 pi / n, period n
         for q in range(n // 2 + 1):
-            M[q] = np.cos(2 * pi * q * i / n)
+            r = (q * i) % n
+            M[q] = np.cos(2 * pi * r.astype(dtype) / n)
         for m in range(1, (n + 1) // 2):
-            M[n - m] = -np.sin(2 * pi * m * i / n)
+            r = (m * i) % n
+            M[n - m] = -np.sin(2 * pi * r.astype(dtype) / n)
     return M
 
 
