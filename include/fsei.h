@@ -1,0 +1,167 @@
+/*
+ * fsei.h -- C ABI of the MI355X pressure-projection library (libfsei.so).
+ *
+ * The operation (paper, Sec. 2.1, eqs. NS and NSdiscr0): in a fractional-step
+ * Navier-Stokes scheme the pressure p^{n+1} is only a Lagrange multiplier that
+ * makes the end-of-step velocity divergence free.  Given a provisional
+ * velocity u* on a staggered Cartesian mesh (central second-order differences,
+ * Sec. 2.1), this library computes
+ *
+ *     f = D u* / dt,   p = L^+ f   (L = D G),   u = u* - dt G p,
+ *
+ * with a direct solver: transforms in the two uniform directions x, y (DCT-II
+ * for walls, real DFT for periodic), one tridiagonal solve along the
+ * stretched wall-normal direction z per (kx, ky) mode, inverse transforms, and
+ * the gradient correction.  The zero mode is pinned by the volume-weighted
+ * mean, sum_c V_c p_c = 0.
+ *
+ * Grid and layout (all entry points):
+ *   - nx x ny x nz pressure cells; dx, dy uniform; z faces zc[0..nz] strictly
+ *     increasing (wall-normal, walls at zc[0] and zc[nz]).
+ *   - Every field is a contiguous (nz, ny, nx) array, x fastest, element
+ *     (k, j, i) at offset (k*ny + j)*nx + i.
+ *   - p[k,j,i] lives at the cell centre; u[k,j,i] on the low x-face of the
+ *     cell, v[k,j,i] on the low y-face, w[k,j,i] on the low z-face.
+ *   - Wall faces (u[:,:,0] for x walls, v[:,0,:] for y walls, w[0,:,:]
+ *     always) are ignored on input and written 0 on output.
+ *
+ * Memory ownership: all field pointers are HIP device pointers owned by the
+ * caller.  The plan owns only host memory.  Device workspace is provided by
+ * the caller (fsei_plan_set_workspace) and never freed by the library.
+ *
+ * Execution: every call enqueues kernels on the plan's stream and returns
+ * without waiting, except (a) when an fsei_info pointer is passed (the call
+ * then waits for the stream to read back scalars) and (b) FP32_REFINE with
+ * rtol > 0 (one scalar is read back per refinement iteration).  A plan is not
+ * thread-safe; calls that share a plan must be serialised by the caller.
+ *
+ * Errors: arguments are checked before anything is launched; no C++
+ * exception crosses this interface.  A failing HIP call is reported as
+ * FSEI_ERR_HIP.
+ */
+#ifndef FSEI_H
+#define FSEI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fsei_plan fsei_plan;
+
+typedef enum {
+    FSEI_OK = 0,
+    FSEI_ERR_ARG = -1,           /* null pointer, bad enum, non-finite or non-positive scalar */
+    FSEI_ERR_SIZE = -2,          /* n < 2, n > 2048, or n not of the form 2^a 3^b (x and y); nz < 2 or nz > 2048 */
+    FSEI_ERR_GRID = -3,          /* zc not finite or not strictly increasing; dx or dy <= 0 */
+    FSEI_ERR_WORKSPACE = -4,     /* no workspace set, or smaller than fsei_plan_workspace_size, or not 256-B aligned */
+    FSEI_ERR_HIP = -5,           /* a HIP runtime call or kernel launch failed */
+    FSEI_ERR_NOT_CONVERGED = -6, /* FP32_REFINE did not reach rtol in max_iter corrections; outputs hold the last iterate */
+    FSEI_ERR_PRECISION = -7      /* entry point does not match the plan's precision mode */
+} fsei_status;
+
+/* Boundary condition of the x and y directions (z always has walls). */
+enum { FSEI_BC_PERIODIC = 0, FSEI_BC_WALL = 1 };
+
+/* Arithmetic of the solve.
+ *   FP64        : every step in double precision.
+ *   FP32_REFINE : FP64 input/output; transforms and tridiagonal sweeps in
+ *                 FP32 (lines of the near-singular lowest modes in FP64), the
+ *                 residual f - L p in FP64, FP32 correction solves until
+ *                 ||f - L p||_2 / ||f||_2 <= rtol or max_iter corrections.
+ *   FP32        : float input/output, FP32 arithmetic (lowest-mode lines in
+ *                 FP64); used by the *_f32 entry points. */
+enum { FSEI_PREC_FP64 = 0, FSEI_PREC_FP32_REFINE = 1, FSEI_PREC_FP32 = 2 };
+
+typedef struct {
+    int iterations;            /* FP32_REFINE correction solves done (0 otherwise) */
+    double rel_residual;       /* ||f - L p||_2 / ||f||_2 when measured (FP32_REFINE), else -1 */
+    double rhs_vmean_removed;  /* volume-weighted mean of f removed before the solve */
+} fsei_info;
+
+/* Create a plan (host only; no device memory, no HIP call).
+ *   nx, ny : cells in x, y (2 <= n <= 2048, n = 2^a 3^b)
+ *   nz     : cells in z (2 <= nz <= 2048)
+ *   bc     : bc[0] for x, bc[1] for y, each FSEI_BC_PERIODIC or FSEI_BC_WALL
+ *   dx, dy : uniform spacings (> 0)
+ *   zc     : HOST array of nz+1 z-face coordinates, strictly increasing; copied
+ *   out    : receives the plan (set to NULL on error)
+ * Defaults: FP64 precision, null stream, no workspace. */
+fsei_status fsei_poisson_plan_create(int nx, int ny, int nz, const int bc[2], double dx, double dy,
+                                     const double* zc, fsei_plan** out);
+
+/* Destroy a plan (host memory only; NULL is accepted). */
+void fsei_poisson_plan_destroy(fsei_plan* plan);
+
+/* Select the precision mode (FSEI_PREC_*).  rtol >= 0 (0 = run exactly
+ * max_iter corrections without reading back residuals); 0 <= max_iter <= 64;
+ * both only matter for FP32_REFINE.  Changes the workspace size and layout: a
+ * workspace set before is dropped, so call this before
+ * fsei_plan_workspace_size / fsei_plan_set_workspace. */
+fsei_status fsei_plan_set_precision(fsei_plan* plan, int precision, double rtol, int max_iter);
+
+/* Bytes of device workspace the plan needs in its current precision mode. */
+fsei_status fsei_plan_workspace_size(const fsei_plan* plan, size_t* bytes);
+
+/* Hand the plan a device buffer of at least fsei_plan_workspace_size bytes,
+ * 256-byte aligned.  Uploads the metric, eigenvalue and twiddle tables with a
+ * synchronous copy.  The buffer stays owned by the caller and must outlive its
+ * use by the plan. */
+fsei_status fsei_plan_set_workspace(fsei_plan* plan, void* device_ptr, size_t bytes);
+
+/* Stream (a hipStream_t passed as void*) on which all work is enqueued. NULL =
+ * the null stream. */
+fsei_status fsei_plan_set_stream(fsei_plan* plan, void* hip_stream);
+
+/* Poisson solve p = L^+ f (double I/O; FP64 or FP32_REFINE plans).
+ *   f : device, (nz,ny,nx) doubles, read only
+ *   p : device, (nz,ny,nx) doubles, written; may alias f
+ *   info : optional (host); when given the call waits for the stream. */
+fsei_status fsei_poisson_solve(fsei_plan* plan, const double* f, double* p, fsei_info* info);
+
+/* Projection (double I/O; FP64 or FP32_REFINE plans).
+ *   u, v, w : device, in: provisional velocity u*, out: projected velocity
+ *   p       : device, out: pressure (V-mean zero); may be NULL
+ *   dt      : time step (> 0, finite)
+ *   info    : optional (host); when given the call waits for the stream. */
+fsei_status fsei_project(fsei_plan* plan, double* u, double* v, double* w, double* p, double dt,
+                         fsei_info* info);
+
+/* Adjoint of fsei_project with respect to u* (double I/O; FP64 or
+ * FP32_REFINE plans, computed in FP64):
+ *   g_u* = P^T g_u + (1/dt) D^T (L^+)^T g_p,  P = I - G L^+ D,
+ * evaluated as transposed stencils with the stretched-grid metric weights, the
+ * transposed per-mode tridiagonal and the transforms in reverse order.
+ *   gu, gv, gw : device, in: dLoss/du, out: dLoss/du*
+ *   gp         : device, dLoss/dp (read only) or NULL
+ *   dt         : the time step of the forward call. */
+fsei_status fsei_project_backward(fsei_plan* plan, double* gu, double* gv, double* gw, const double* gp,
+                                  double dt);
+
+/* FP32 variants (FSEI_PREC_FP32 plans), same conventions with float fields. */
+fsei_status fsei_project_f32(fsei_plan* plan, float* u, float* v, float* w, float* p, float dt);
+fsei_status fsei_project_backward_f32(fsei_plan* plan, float* gu, float* gv, float* gw, const float* gp,
+                                      float dt);
+
+/* Per-kernel timing with HIP events on the plan's stream (for measurement).
+ * enable != 0 records an event pair around every launch from now on;
+ * fsei_plan_reset_timing clears the accumulators. */
+fsei_status fsei_plan_set_timing(fsei_plan* plan, int enable);
+fsei_status fsei_plan_reset_timing(fsei_plan* plan);
+
+/* Read the accumulated timing of kernel slot `slot` (0 <= slot < FSEI_NUM_KERNEL_SLOTS):
+ * total milliseconds and launch count (waits for the stream).  name receives
+ * a static string naming the slot's kernel. */
+#define FSEI_NUM_KERNEL_SLOTS 16
+fsei_status fsei_plan_kernel_time(fsei_plan* plan, int slot, double* total_ms, long* launches,
+                                  const char** name);
+
+/* Static description of a status code. */
+const char* fsei_status_string(fsei_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSEI_H */

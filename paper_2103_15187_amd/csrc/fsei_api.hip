@@ -1,0 +1,647 @@
+// HIP side of the C ABI: workspace upload, kernel launches on the plan's
+// stream, precision modes, refinement loop, per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <type_traits>
+#include <vector>
+
+#include "fsei_kernels.h"
+#include "fsei_plan.h"
+
+using namespace fsei;
+using namespace fsei::dev;
+
+namespace {
+
+constexpr int kThrX = 256;
+constexpr int kEmaxY = 2048, kThrY = 256;
+
+const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
+    "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
+    "zsolve_fp64_lines", "", "", "", "", ""};
+constexpr int K_ZLIST = 10;
+
+struct PendingEv {
+    hipEvent_t a, b;
+    int slot;
+};
+
+struct TimingState {
+    std::vector<PendingEv> pending;
+    std::vector<hipEvent_t> free_ev;
+};
+
+TimingState& tstate(fsei_plan* p) {
+    // one state per plan, owned through ev_pool[0]
+    if (p->ev_pool.empty()) p->ev_pool.push_back(new TimingState());
+    return *static_cast<TimingState*>(p->ev_pool[0]);
+}
+
+hipEvent_t get_event(TimingState& ts) {
+    if (!ts.free_ev.empty()) {
+        hipEvent_t e = ts.free_ev.back();
+        ts.free_ev.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+void harvest(fsei_plan* p) {
+    TimingState& ts = tstate(p);
+    for (auto& pe : ts.pending) {
+        (void)hipEventSynchronize(pe.b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, pe.a, pe.b);
+        p->t_ms[pe.slot] += ms;
+        p->t_count[pe.slot] += 1;
+        ts.free_ev.push_back(pe.a);
+        ts.free_ev.push_back(pe.b);
+    }
+    ts.pending.clear();
+}
+
+// Brackets one launch with events when timing is on.
+struct Timed {
+    fsei_plan* p;
+    int slot;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(fsei_plan* pl, int s) : p(pl), slot(s) {
+        if (p->timing) {
+            TimingState& ts = tstate(p);
+            if (ts.pending.size() > 4096) harvest(p);
+            a = get_event(ts);
+            b = get_event(ts);
+            (void)hipEventRecord(a, (hipStream_t)p->stream);
+        }
+    }
+    ~Timed() {
+        if (p->timing) {
+            (void)hipEventRecord(b, (hipStream_t)p->stream);
+            tstate(p).pending.push_back({a, b, slot});
+        }
+    }
+};
+
+template <typename T>
+const T* tab(const fsei_plan* p, int id);
+template <>
+const double* tab<double>(const fsei_plan* p, int id) {
+    return reinterpret_cast<const double*>((const char*)p->ws + p->ws_tab_d) + p->tab_off[id];
+}
+template <>
+const float* tab<float>(const fsei_plan* p, int id) {
+    return reinterpret_cast<const float*>((const char*)p->ws + p->ws_tab_f) + p->tab_off[id];
+}
+
+double* scalars(const fsei_plan* p) { return reinterpret_cast<double*>((char*)p->ws + p->ws_scalars); }
+double* partials(const fsei_plan* p) { return reinterpret_cast<double*>((char*)p->ws + p->ws_partials); }
+void* field1(const fsei_plan* p) { return (char*)p->ws + p->ws_field; }
+void* field2(const fsei_plan* p) { return (char*)p->ws + p->ws_field2; }
+void* field3(const fsei_plan* p) { return (char*)p->ws + p->ws_field3; }
+int* zlist(const fsei_plan* p) { return reinterpret_cast<int*>((char*)p->ws + p->ws_list); }
+
+int nseq_x(const fsei_plan* p) { return std::max(1, kEmaxX / p->nx); }
+int nseq_y(const fsei_plan* p) { return std::max(1, kEmaxY / p->ny); }
+long xblocks(const fsei_plan* p) {
+    const long nl = 2L * nseq_x(p);
+    return ((long)p->ny * p->nz + nl - 1) / nl;
+}
+
+hipStream_t S(const fsei_plan* p) { return (hipStream_t)p->stream; }
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename TI, typename TO, int PRO>
+void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.bcy = p->bcy;
+    a.nseq = nseq_x(p);
+    a.fp = p->fx;
+    a.twc = tab<TO>(p, T_TWX_C);
+    a.tws = tab<TO>(p, T_TWX_S);
+    a.dctc = tab<TO>(p, T_DCTX_C);
+    a.dcts = tab<TO>(p, T_DCTX_S);
+    Timed t(p, slot);
+    hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, kEmaxX, kThrX>), dim3((unsigned)xblocks(p)), dim3(kThrX), 0, S(p), a);
+}
+
+template <typename T, typename TP, int EPI>
+void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot) {
+    XInvArgs<T, TP> a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.nseq = nseq_x(p);
+    a.fp = p->fx;
+    a.in = in;
+    a.out = out;
+    a.twc = tab<T>(p, T_TWX_C);
+    a.tws = tab<T>(p, T_TWX_S);
+    a.dctc = tab<T>(p, T_DCTX_C);
+    a.dcts = tab<T>(p, T_DCTX_S);
+    Timed t(p, slot);
+    hipLaunchKernelGGL((k_xinv<T, TP, EPI, kEmaxX, kThrX>), dim3((unsigned)xblocks(p)), dim3(kThrX), 0, S(p), a);
+}
+
+template <typename T>
+void launch_y(fsei_plan* p, T* data, bool inverse) {
+    YArgs<T> a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcy = p->bcy;
+    a.nseq = nseq_y(p);
+    const int tx = 2 * a.nseq;
+    a.ntile = (p->nx + tx - 1) / tx;
+    a.fp = p->fy;
+    a.data = data;
+    a.twc = tab<T>(p, T_TWY_C);
+    a.tws = tab<T>(p, T_TWY_S);
+    a.dctc = tab<T>(p, T_DCTY_C);
+    a.dcts = tab<T>(p, T_DCTY_S);
+    const unsigned nb = (unsigned)(a.ntile * p->nz);
+    if (inverse) {
+        Timed t(p, K_YINV);
+        hipLaunchKernelGGL((k_yinv<T, kEmaxY, kThrY>), dim3(nb), dim3(kThrY), 0, S(p), a);
+    } else {
+        Timed t(p, K_YFWD);
+        hipLaunchKernelGGL((k_yfwd<T, kEmaxY, kThrY>), dim3(nb), dim3(kThrY), 0, S(p), a);
+    }
+}
+
+// chunking of the z lines: P chunks of exactly L rows (L one of the compiled
+// sizes), the last chunk padded with decoupled rows; P <= pmax
+bool choose_chunks(int nz, int pmax, int* L, int* P) {
+    static const int sizes[] = {4, 8, 12, 16, 24, 32};
+    for (int l : sizes) {
+        const int pc = (nz + l - 1) / l;
+        if (pc <= pmax) {
+            *L = l;
+            *P = pc;
+            return true;
+        }
+    }
+    return false;
+}
+
+template <typename TS, typename TC, int TXL, int NT, bool LIST>
+void z_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid, int slot) {
+    const size_t dyn = 0;
+    Timed t(p, slot);
+    switch (a.L) {
+        case 4: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 4, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+        case 8: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 8, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+        case 12: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 12, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+        case 16: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 16, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+        case 24: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 24, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+        default: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 32, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+    }
+}
+
+template <typename TS, typename TC>
+ZArgs<TS, TC> zargs(const fsei_plan* p, TS* data, int transposed) {
+    ZArgs<TS, TC> a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.transposed = transposed;
+    a.data = data;
+    a.scale = (TC)(1.0 / ((double)p->nx * (double)p->ny));
+    a.za = tab<TC>(p, T_ZA);
+    a.zc = tab<TC>(p, T_ZC);
+    a.zb0 = tab<TC>(p, T_ZB0);
+    a.dz = tab<TC>(p, T_DZ);
+    a.inv_dz = tab<TC>(p, T_INV_DZ);
+    a.lamx = tab<TC>(p, T_LAMX);
+    a.lamy = tab<TC>(p, T_LAMY);
+    return a;
+}
+
+// z solve of every mode line of `data` (in place), zero mode included
+template <typename TS>
+void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
+    constexpr bool F32 = std::is_same<TS, float>::value;
+    const int nz = p->nz;
+    if constexpr (!F32) {
+        ZArgs<double, double> a = zargs<double, double>(p, data, transposed);
+        a.sigma_thr = 0.0;
+        int L, P;
+        if (choose_chunks(nz, 32, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z_dispatch<double, double, 16, 512, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
+        } else {
+            choose_chunks(nz, 64, &L, &P);
+            a.L = L;
+            a.P = P;
+            z_dispatch<double, double, 8, 512, false>(p, a, dim3((p->nx + 7) / 8, p->ny), K_ZSOLVE);
+        }
+    } else {
+        ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
+        a.sigma_thr = (float)p->sigma_thr;
+        int L, P;
+        if (choose_chunks(nz, 32, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z_dispatch<float, float, 32, 1024, false>(p, a, dim3((p->nx + 31) / 32, p->ny), K_ZSOLVE);
+        } else {
+            choose_chunks(nz, 64, &L, &P);
+            a.L = L;
+            a.P = P;
+            z_dispatch<float, float, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
+        }
+        if (p->nlist > 0) {
+            ZArgs<float, double> b = zargs<float, double>(p, data, transposed);
+            b.list = zlist(p);
+            b.nlist = p->nlist;
+            if (choose_chunks(nz, 32, &L, &P)) {
+                b.L = L;
+                b.P = P;
+                z_dispatch<float, double, 16, 512, true>(p, b, dim3((p->nlist + 15) / 16), K_ZLIST);
+            } else {
+                choose_chunks(nz, 64, &L, &P);
+                b.L = L;
+                b.P = P;
+                z_dispatch<float, double, 8, 512, true>(p, b, dim3((p->nlist + 7) / 8), K_ZLIST);
+            }
+        }
+    }
+    ZeroArgs<TS> z{};
+    z.nz = nz;
+    z.transposed = transposed;
+    z.stride = (size_t)p->nx * p->ny;
+    z.data = data;
+    z.scale = 1.0 / ((double)p->nx * (double)p->ny);
+    z.lz = p->lz;
+    z.dz = tab<double>(p, T_DZ);
+    z.inv_dz = tab<double>(p, T_INV_DZ);
+    z.h = tab<double>(p, T_H);
+    z.scal = record_mean ? scalars(p) : nullptr;
+    Timed t(p, K_PREP);
+    hipLaunchKernelGGL((k_zero_mode<TS>), dim3(1), dim3(256), 0, S(p), z);
+}
+
+template <typename TIO, typename TP>
+void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoint, double dt) {
+    GradArgs<TIO, TP> a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.bcy = p->bcy;
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.p = pr;
+    if (!adjoint) {
+        a.cx = (TIO)(-dt / p->dx);
+        a.cy = (TIO)(-dt / p->dy);
+        a.sw = (TIO)(-dt);
+        a.bk = tab<TIO>(p, T_INV_H);
+        a.gk = tab<TIO>(p, T_INV_H);
+    } else {
+        a.cx = (TIO)(1.0 / p->dx);
+        a.cy = (TIO)(1.0 / p->dy);
+        a.sw = (TIO)1;
+        a.bk = tab<TIO>(p, T_INV_DZ);
+        a.gk = tab<TIO>(p, T_GAM_ADJ);
+    }
+    Timed t(p, K_GRAD);
+    hipLaunchKernelGGL((k_grad<TIO, TP>), dim3((p->nx + 255) / 256, p->ny, p->nz), dim3(256), 0, S(p), a);
+}
+
+template <typename TI, typename TO>
+XFwdArgs<TI, TO> div_args(const fsei_plan* p, const TI* u, const TI* v, const TI* w, const TI* gp, bool adjoint,
+                          double dt) {
+    XFwdArgs<TI, TO> a{};
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.gp = gp;
+    a.idx = (TI)(1.0 / p->dx);
+    a.idy = (TI)(1.0 / p->dy);
+    if (!adjoint) {
+        a.alpha = (TI)(1.0 / dt);
+        a.beta = (TI)0;
+        a.zeta = tab<TI>(p, T_INV_DZ);
+        a.eta = tab<TI>(p, T_INV_DZ);
+    } else {
+        a.alpha = (TI)-1;
+        a.beta = (TI)(-1.0 / dt);
+        a.zeta = tab<TI>(p, T_ZETA_ADJ);
+        a.eta = tab<TI>(p, T_INV_H);
+    }
+    return a;
+}
+
+fsei_status check_hip() {
+    return (hipGetLastError() == hipSuccess) ? FSEI_OK : FSEI_ERR_HIP;
+}
+
+fsei_status ready(const fsei_plan* p) {
+    if (!p) return FSEI_ERR_ARG;
+    if (!p->ws || p->ws_bytes < p->ws_total) return FSEI_ERR_WORKSPACE;
+    return FSEI_OK;
+}
+
+bool good_dt(double dt) { return std::isfinite(dt) && dt > 0.0; }
+
+fsei_status read_scalars(fsei_plan* p, double* host, int n) {
+    if (hipMemcpyAsync(host, scalars(p), n * sizeof(double), hipMemcpyDeviceToHost, S(p)) != hipSuccess)
+        return FSEI_ERR_HIP;
+    if (hipStreamSynchronize(S(p)) != hipSuccess) return FSEI_ERR_HIP;
+    return FSEI_OK;
+}
+
+// residual norm^2 (and sum) of the last RESID/xfwd pass into scalars[off..off+1]
+void reduce_partials(fsei_plan* p, int off) {
+    Timed t(p, K_NORM);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, S(p), (const double*)partials(p), (int)xblocks(p),
+                       scalars(p) + off);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 + FP64 iterative refinement.  f (FP64) is the right-hand side; on
+// return p64 holds the pressure.
+//   p0 = solve32(f); repeat: r = (f - mean) - L p (FP64 stencil), stop when
+//   ||r|| <= rtol ||f - mean||, else p += solve32(r).
+// ---------------------------------------------------------------------------
+template <int PRO>
+fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p64, fsei_info* info) {
+    float* w32 = static_cast<float*>(field2(p));
+    double* f64 = static_cast<double*>(field1(p));
+    first.out = w32;
+    first.out_f = f64;
+    first.partials = partials(p);
+    launch_xfwd<double, float, PRO>(p, first, K_XFWD);
+    reduce_partials(p, 1);   // scalars[1] = sum f^2, scalars[2] = sum f
+    launch_y<float>(p, w32, false);
+    launch_z<float>(p, w32, 0, true);   // scalars[0] = removed V-mean
+    launch_y<float>(p, w32, true);
+    launch_xinv<float, double, EPI_STORE>(p, w32, p64, K_XINV);
+    const double N = (double)p->ncells();
+    auto rel_from = [&](const double* h) {
+        // ||f - mean||^2 = sum f^2 - 2 mean sum f + N mean^2
+        const double mean = h[0];
+        double fn2 = h[1] - 2.0 * mean * h[2] + N * mean * mean;
+        if (fn2 <= 0.0) fn2 = h[1];
+        return (fn2 > 0.0) ? std::sqrt(h[3] / fn2) : 0.0;
+    };
+    XFwdArgs<double, float> r{};
+    r.f = f64;
+    r.p = p64;
+    r.idx2 = 1.0 / (p->dx * p->dx);
+    r.idy2 = 1.0 / (p->dy * p->dy);
+    r.za = tab<double>(p, T_ZA);
+    r.zc = tab<double>(p, T_ZC);
+    r.scal = scalars(p);
+    r.partials = partials(p);
+    int it = 0;
+    double rel = -1.0;
+    bool converged = false;
+    for (; it < p->max_iter; ++it) {
+        r.out = w32;
+        launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+        if (p->rtol > 0.0) {
+            reduce_partials(p, 3);
+            double h[5];
+            fsei_status st = read_scalars(p, h, 5);
+            if (st != FSEI_OK) return st;
+            rel = rel_from(h);
+            if (rel <= p->rtol) {
+                converged = true;
+                break;
+            }
+        }
+        launch_y<float>(p, w32, false);
+        launch_z<float>(p, w32, 0, false);
+        launch_y<float>(p, w32, true);
+        launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC);
+    }
+    const bool need_final = (p->rtol > 0.0 && !converged) || (info != nullptr && !converged);
+    if (need_final) {
+        r.out = nullptr;   // norm only
+        launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+        reduce_partials(p, 3);
+        double h[5];
+        fsei_status st = read_scalars(p, h, 5);
+        if (st != FSEI_OK) return st;
+        rel = rel_from(h);
+        if (p->rtol > 0.0 && rel <= p->rtol) converged = true;
+    }
+    if (info) {
+        double h[1];
+        fsei_status st = read_scalars(p, h, 1);
+        if (st != FSEI_OK) return st;
+        info->iterations = it;
+        info->rel_residual = rel;
+        info->rhs_vmean_removed = h[0];
+    }
+    fsei_status st = check_hip();
+    if (st != FSEI_OK) return st;
+    if (p->rtol > 0.0 && !converged) return FSEI_ERR_NOT_CONVERGED;
+    return FSEI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fsei_poisson_plan_destroy(fsei_plan* p) {
+    if (!p) return;
+    if (!p->ev_pool.empty()) {
+        TimingState* ts = static_cast<TimingState*>(p->ev_pool[0]);
+        for (auto& pe : ts->pending) {
+            (void)hipEventDestroy(pe.a);
+            (void)hipEventDestroy(pe.b);
+        }
+        for (auto e : ts->free_ev) (void)hipEventDestroy(e);
+        delete ts;
+    }
+    delete p;
+}
+
+fsei_status fsei_plan_set_workspace(fsei_plan* p, void* dev, size_t bytes) {
+    if (!p || !dev) return FSEI_ERR_ARG;
+    if (((uintptr_t)dev % kAlign) != 0 || bytes < p->ws_total) return FSEI_ERR_WORKSPACE;
+    if (hipMemcpy((char*)dev + p->ws_tab_d, p->tab_d.data(), p->tab_d.size() * sizeof(double),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return FSEI_ERR_HIP;
+    if (hipMemcpy((char*)dev + p->ws_tab_f, p->tab_f.data(), p->tab_f.size() * sizeof(float),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return FSEI_ERR_HIP;
+    if (!p->list_host.empty()) {
+        if (hipMemcpy((char*)dev + p->ws_list, p->list_host.data(), p->list_host.size() * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return FSEI_ERR_HIP;
+    }
+    if (hipMemset((char*)dev + p->ws_scalars, 0, fsei_plan_impl::kScalars * sizeof(double)) != hipSuccess)
+        return FSEI_ERR_HIP;
+    p->ws = dev;
+    p->ws_bytes = bytes;
+    return FSEI_OK;
+}
+
+fsei_status fsei_plan_set_stream(fsei_plan* p, void* stream) {
+    if (!p) return FSEI_ERR_ARG;
+    p->stream = stream;
+    return FSEI_OK;
+}
+
+fsei_status fsei_poisson_solve(fsei_plan* p, const double* f, double* out, fsei_info* info) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!f || !out) return FSEI_ERR_ARG;
+    if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    if (p->precision == FSEI_PREC_FP32_REFINE) {
+        XFwdArgs<double, float> a{};
+        a.f = f;
+        return refine_solve<PRO_COPY>(p, a, out, info);
+    }
+    XFwdArgs<double, double> a{};
+    a.f = f;
+    a.out = out;
+    launch_xfwd<double, double, PRO_COPY>(p, a, K_XFWD);
+    launch_y<double>(p, out, false);
+    launch_z<double>(p, out, 0, true);
+    launch_y<double>(p, out, true);
+    launch_xinv<double, double, EPI_STORE>(p, out, out, K_XINV);
+    st = check_hip();
+    if (st != FSEI_OK) return st;
+    if (info) {
+        double h[1];
+        st = read_scalars(p, h, 1);
+        if (st != FSEI_OK) return st;
+        info->iterations = 0;
+        info->rel_residual = -1.0;
+        info->rhs_vmean_removed = h[0];
+    }
+    return FSEI_OK;
+}
+
+fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* pout, double dt, fsei_info* info) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!u || !v || !w) return FSEI_ERR_ARG;
+    if (!good_dt(dt)) return FSEI_ERR_ARG;
+    if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    if (p->precision == FSEI_PREC_FP32_REFINE) {
+        double* p64 = pout ? pout : static_cast<double*>(field3(p));
+        XFwdArgs<double, float> a = div_args<double, float>(p, u, v, w, nullptr, false, dt);
+        st = refine_solve<PRO_DIV>(p, a, p64, info);
+        if (st != FSEI_OK && st != FSEI_ERR_NOT_CONVERGED) return st;
+        launch_grad<double, double>(p, u, v, w, p64, false, dt);
+        fsei_status st2 = check_hip();
+        return (st2 != FSEI_OK) ? st2 : st;
+    }
+    double* buf = pout ? pout : static_cast<double*>(field1(p));
+    XFwdArgs<double, double> a = div_args<double, double>(p, u, v, w, nullptr, false, dt);
+    a.out = buf;
+    launch_xfwd<double, double, PRO_DIV>(p, a, K_XFWD);
+    launch_y<double>(p, buf, false);
+    launch_z<double>(p, buf, 0, true);
+    launch_y<double>(p, buf, true);
+    launch_xinv<double, double, EPI_STORE>(p, buf, buf, K_XINV);
+    launch_grad<double, double>(p, u, v, w, buf, false, dt);
+    st = check_hip();
+    if (st != FSEI_OK) return st;
+    if (info) {
+        double h[1];
+        st = read_scalars(p, h, 1);
+        if (st != FSEI_OK) return st;
+        info->iterations = 0;
+        info->rel_residual = -1.0;
+        info->rhs_vmean_removed = h[0];
+    }
+    return FSEI_OK;
+}
+
+fsei_status fsei_project_backward(fsei_plan* p, double* gu, double* gv, double* gw, const double* gp, double dt) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!gu || !gv || !gw) return FSEI_ERR_ARG;
+    if (!good_dt(dt)) return FSEI_ERR_ARG;
+    if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    double* buf = static_cast<double*>(field1(p));
+    XFwdArgs<double, double> a = div_args<double, double>(p, gu, gv, gw, gp, true, dt);
+    a.out = buf;
+    launch_xfwd<double, double, PRO_DIV_ADJ>(p, a, K_XFWD);
+    launch_y<double>(p, buf, false);
+    launch_z<double>(p, buf, 1, false);
+    launch_y<double>(p, buf, true);
+    launch_xinv<double, double, EPI_STORE>(p, buf, buf, K_XINV);
+    launch_grad<double, double>(p, gu, gv, gw, buf, true, dt);
+    return check_hip();
+}
+
+fsei_status fsei_project_f32(fsei_plan* p, float* u, float* v, float* w, float* pout, float dt) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!u || !v || !w) return FSEI_ERR_ARG;
+    if (!good_dt(dt)) return FSEI_ERR_ARG;
+    if (p->precision != FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    float* buf = pout ? pout : static_cast<float*>(field1(p));
+    XFwdArgs<float, float> a = div_args<float, float>(p, u, v, w, nullptr, false, dt);
+    a.out = buf;
+    launch_xfwd<float, float, PRO_DIV>(p, a, K_XFWD);
+    launch_y<float>(p, buf, false);
+    launch_z<float>(p, buf, 0, true);
+    launch_y<float>(p, buf, true);
+    launch_xinv<float, float, EPI_STORE>(p, buf, buf, K_XINV);
+    launch_grad<float, float>(p, u, v, w, buf, false, dt);
+    return check_hip();
+}
+
+fsei_status fsei_project_backward_f32(fsei_plan* p, float* gu, float* gv, float* gw, const float* gp, float dt) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!gu || !gv || !gw) return FSEI_ERR_ARG;
+    if (!good_dt(dt)) return FSEI_ERR_ARG;
+    if (p->precision != FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    float* buf = static_cast<float*>(field1(p));
+    XFwdArgs<float, float> a = div_args<float, float>(p, gu, gv, gw, gp, true, dt);
+    a.out = buf;
+    launch_xfwd<float, float, PRO_DIV_ADJ>(p, a, K_XFWD);
+    launch_y<float>(p, buf, false);
+    launch_z<float>(p, buf, 1, false);
+    launch_y<float>(p, buf, true);
+    launch_xinv<float, float, EPI_STORE>(p, buf, buf, K_XINV);
+    launch_grad<float, float>(p, gu, gv, gw, buf, true, dt);
+    return check_hip();
+}
+
+fsei_status fsei_plan_set_timing(fsei_plan* p, int enable) {
+    if (!p) return FSEI_ERR_ARG;
+    p->timing = enable != 0;
+    return FSEI_OK;
+}
+
+fsei_status fsei_plan_reset_timing(fsei_plan* p) {
+    if (!p) return FSEI_ERR_ARG;
+    harvest(p);
+    for (int s = 0; s < FSEI_NUM_KERNEL_SLOTS; ++s) {
+        p->t_ms[s] = 0.0;
+        p->t_count[s] = 0;
+    }
+    return FSEI_OK;
+}
+
+fsei_status fsei_plan_kernel_time(fsei_plan* p, int slot, double* total_ms, long* launches, const char** name) {
+    if (!p || slot < 0 || slot >= FSEI_NUM_KERNEL_SLOTS) return FSEI_ERR_ARG;
+    harvest(p);
+    if (total_ms) *total_ms = p->t_ms[slot];
+    if (launches) *launches = p->t_count[slot];
+    if (name) *name = kSlotNames[slot];
+    return FSEI_OK;
+}
+
+}  // extern "C"

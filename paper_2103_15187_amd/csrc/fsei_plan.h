@@ -1,0 +1,115 @@
+// Internal plan structure shared by the host-only plan code (fsei_plan.cpp)
+// and the HIP entry points (fsei_api.hip).  No HIP types appear here, so the
+// plan logic builds and runs on a machine without a GPU.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/fsei.h"
+
+namespace fsei {
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxN = 2048;     // longest x/y transform
+constexpr int kMaxNz = 2048;    // longest z line
+constexpr size_t kAlign = 256;
+constexpr int kEmaxX = 2048;   // complex elements per x-transform workgroup
+
+// Radix schedule of one complex FFT length (radices 8, 4, 2, 3).
+struct FftPlan {
+    int n = 0;
+    int nstages = 0;
+    int radix[kMaxStages] = {0};
+};
+
+// Names of the per-k / per-mode / twiddle tables stored on the device, each
+// in double and in float.  The order is the order inside the table block.
+enum TableId {
+    T_ZA = 0,      // a_k  = 1/(dz_k h_k), k>=1; a_0 = 0            (nz)
+    T_ZC,          // c_k  = 1/(dz_k h_{k+1}), k<=nz-2; c_{nz-1}=0  (nz)
+    T_ZB0,         // -(a_k + c_k)                                    (nz)
+    T_DZ,          // dz_k                                            (nz)
+    T_INV_DZ,      // 1/dz_k                                          (nz)
+    T_INV_H,       // 1/h_k, k>=1; 0 at k=0                           (nz)
+    T_H,           // h_k = zm_k - zm_{k-1}, k>=1; 0 at k=0          (nz)
+    T_ZETA_ADJ,    // 1/h_{k+1} for k<=nz-2, 0 at nz-1                (nz)
+    T_GAM_ADJ,     // 1/dz_{k-1} for k>=1, 0 at k=0                   (nz)
+    T_LAMX,        // modified wavenumbers of x rows                  (nx)
+    T_LAMY,        // modified wavenumbers of y rows                  (ny)
+    T_TWX_C,       // cos(2 pi t / nx)                                (nx)
+    T_TWX_S,       // sin(2 pi t / nx)                                (nx)
+    T_DCTX_C,      // cos(pi m / (2 nx))                              (nx)
+    T_DCTX_S,      // sin(pi m / (2 nx))                              (nx)
+    T_TWY_C,       // cos(2 pi t / ny)                                (ny)
+    T_TWY_S,       // sin(2 pi t / ny)                                (ny)
+    T_DCTY_C,      // cos(pi m / (2 ny))                              (ny)
+    T_DCTY_S,      // sin(pi m / (2 ny))                              (ny)
+    T_COUNT
+};
+
+// Kernel slots for per-kernel timing.
+enum KernelSlot {
+    K_XFWD = 0, K_YFWD, K_ZSOLVE, K_YINV, K_XINV, K_GRAD, K_RESID_XFWD, K_XINV_ACC,
+    K_NORM, K_PREP, K_SLOT_COUNT
+};
+
+struct fsei_plan_impl {
+    int nx = 0, ny = 0, nz = 0, bcx = 0, bcy = 0;
+    double dx = 0, dy = 0;
+    std::vector<double> zc, dz, h;   // h[0] unused (0)
+    double lz = 0;
+    double dzmin = 0;
+
+    FftPlan fx, fy;
+
+    int precision = FSEI_PREC_FP64;
+    double rtol = 1e-10;
+    int max_iter = 4;
+    double kappa_star = 1e4;
+
+    // host copies of the device tables
+    std::vector<double> tab_d;
+    std::vector<float> tab_f;
+    size_t tab_off[T_COUNT] = {0};   // element offsets inside tab_d / tab_f
+    size_t tab_elems = 0;
+
+    // workspace layout (byte offsets)
+    size_t ws_tab_d = 0, ws_tab_f = 0, ws_scalars = 0, ws_partials = 0;
+    size_t ws_field = 0, ws_field_bytes = 0;       // main intermediate field
+    size_t ws_field2 = 0, ws_field2_bytes = 0;     // second field (refine: FP32 work field)
+    size_t ws_field3 = 0, ws_field3_bytes = 0;     // refine: FP64 pressure when the caller passes none
+    size_t ws_list = 0, ws_list_bytes = 0;         // mode lines solved in FP64 by FP32 plans
+    size_t ws_total = 0;
+    size_t n_partials = 0;                          // per-block partial sums (pairs)
+    static constexpr int kScalars = 64;
+
+    // FP32 plans: lines with |lambda_x + lambda_y| < sigma_thr (condition
+    // number above kappa_star) are solved in FP64
+    double sigma_thr = 0.0;
+    std::vector<int> list_host;
+    int nlist = 0;
+
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    void* stream = nullptr;
+
+    // timing
+    bool timing = false;
+    double t_ms[FSEI_NUM_KERNEL_SLOTS] = {0};
+    long t_count[FSEI_NUM_KERNEL_SLOTS] = {0};
+    std::vector<void*> ev_pool;          // hipEvent_t pairs, recorded lazily
+    std::vector<int> ev_slot;            // pending (start, stop) pairs -> slot
+    size_t ev_used = 0;
+
+    size_t ncells() const { return (size_t)nx * ny * nz; }
+};
+
+// Host-side helpers (fsei_plan.cpp).
+bool factor_radices(int n, FftPlan* out);
+void compute_layout(fsei_plan_impl* p);
+
+}  // namespace fsei
+
+struct fsei_plan : fsei::fsei_plan_impl {};

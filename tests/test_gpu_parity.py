@@ -1,0 +1,221 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: FP64 path <= 1e-12 relative L2 against the oracle (u, v, w and p, both
+with the V-mean-zero pinning); FP32+refinement <= 1e-10 relative residual;
+plain FP32 <= 2e-5 relative L2 (rounding of ~40 FP32 operations per value
+along the transform chain, amplified by the condition of the lowest modes
+that stay in FP32)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import PERIODIC, WALL
+from paper_2103_15187_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BCS = [(WALL, WALL), (PERIODIC, WALL), (WALL, PERIODIC), (PERIODIC, PERIODIC)]
+
+
+def fsei():
+    from paper_2103_15187_amd import fsei as F
+    return F
+
+
+def grid_of(spec):
+    return oracle.Grid(spec.nx, spec.ny, spec.nz, spec.bcx, spec.bcy, spec.dx, spec.dy, spec.zc())
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def run_project(spec, u, v, w, dt=1.0, **kw):
+    F = fsei()
+    plan = F.Plan.from_spec(spec, **kw)
+    dtype = torch.float32 if kw.get("precision") == F.PREC_FP32 else torch.float64
+    ud, vd, wd = dev(u, dtype), dev(v, dtype), dev(w, dtype)
+    out = plan.project(ud, vd, wd, dt=dt, info=True)
+    torch.cuda.synchronize()
+    p, info = out
+    return host(ud), host(vd), host(wd), host(p), info
+
+
+SMALL = [(4, 6, 8), (8, 8, 8), (6, 3, 5), (12, 16, 10), (3, 4, 7), (2, 2, 2), (16, 12, 33)]
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("dims", SMALL)
+def test_project_fp64_small(bc, dims):
+    nx, ny, nz = dims
+    spec = W.small_spec(nx, ny, nz, bc[0], bc[1], lx=1.3, ly=0.9, lz=2.0, stretch=2.0)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, nx * 7 + ny * 3 + nz)
+    ru, rv, rw, rp = oracle.project(u, v, w, g, dt=0.37)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, dt=0.37)
+    print(f"dims={dims} bc={bc} errs u={rel(gu, ru):.2e} v={rel(gv, rv):.2e} w={rel(gw, rw):.2e} p={rel(gp, rp):.2e}")
+    for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp)):
+        assert rel(a, b) <= 1e-12
+    assert abs(info["rhs_vmean_removed"]) < 1e-10
+
+
+@pytest.mark.parametrize("dims,bc", [((96, 24, 50), (PERIODIC, WALL)), ((768, 6, 20), (WALL, PERIODIC)),
+                                     ((6, 768, 12), (PERIODIC, WALL)), ((48, 96, 130), (WALL, WALL)),
+                                     ((64, 32, 1000), (WALL, WALL))])
+def test_project_fp64_tiles_and_ragged(dims, bc):
+    """Several workgroup tiles per axis, radix-3 lengths, ragged z chunks."""
+    nx, ny, nz = dims
+    spec = W.small_spec(nx, ny, nz, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 5)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, _ = run_project(spec, u, v, w)
+    print(f"dims={dims} errs u={rel(gu, ru):.2e} v={rel(gv, rv):.2e} w={rel(gw, rw):.2e} p={rel(gp, rp):.2e}")
+    for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp)):
+        assert rel(a, b) <= 1e-12
+
+
+def test_project_fp64_c1():
+    spec = W.CONFIGS["C1"]
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, W.SEEDS["C1"])
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, _ = run_project(spec, u, v, w)
+    errs = [rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))]
+    print("C1 errs", errs)
+    assert max(errs) <= 1e-12
+    div = oracle.divergence(gu, gv, gw, g)
+    assert np.abs(div).max() <= 1e-10 * np.abs(oracle.divergence(u, v, w, g)).max()
+
+
+@pytest.mark.parametrize("bc", BCS)
+def test_poisson_solve_incompatible_rhs_and_in_place(bc):
+    F = fsei()
+    spec = W.small_spec(24, 20, 28, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
+    g = grid_of(spec)
+    f = W.rng(3).standard_normal(spec.shape) + 0.25
+    rp, rinfo = oracle.poisson_solve(f, g, return_info=True)
+    plan = F.Plan.from_spec(spec)
+    fd = dev(f)
+    p, info = plan.poisson_solve(fd, info=True)
+    assert rel(host(p), rp) <= 1e-12
+    assert abs(info["rhs_vmean_removed"] - rinfo["rhs_vmean_removed"]) <= 1e-12
+    plan.poisson_solve(fd, fd)                          # p aliases f
+    torch.cuda.synchronize()
+    assert rel(host(fd), rp) <= 1e-12
+
+
+@pytest.mark.parametrize("bc", BCS)
+@pytest.mark.parametrize("with_gp", [False, True])
+def test_backward_fp64_matches_oracle_adjoint(bc, with_gp):
+    F = fsei()
+    spec = W.small_spec(12, 10, 14, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
+    g = grid_of(spec)
+    r = W.rng(17)
+    gu, gv, gw = (r.standard_normal(spec.shape) for _ in range(3))
+    gp = r.standard_normal(spec.shape) if with_gp else None
+    mu, mv, mw = W.dead_face_masks(spec)
+    gu[mu] = 0
+    gv[mv] = 0
+    gw[mw] = 0
+    ref = oracle.project_adjoint(gu, gv, gw, gp, g, dt=0.6)
+    plan = F.Plan.from_spec(spec)
+    a, b, c = dev(gu), dev(gv), dev(gw)
+    plan.project_backward(a, b, c, None if gp is None else dev(gp), dt=0.6)
+    torch.cuda.synchronize()
+    for x, y in zip((host(a), host(b), host(c)), ref):
+        assert rel(x, y) <= 1e-12
+
+
+def test_adjoint_dot_product_identity_c4a_shape():
+    """<P x, y> = <x, P^T y> on the GPU alone at the C4a shape."""
+    F = fsei()
+    spec = W.CONFIGS["C4a"]
+    plan = F.Plan.from_spec(spec)
+    r = W.rng(44)
+    x = [r.standard_normal(spec.shape) for _ in range(3)]
+    y = [r.standard_normal(spec.shape) for _ in range(3)]
+    for arrs in (x, y):
+        for a, m in zip(arrs, W.dead_face_masks(spec)):
+            a[m] = 0
+    xd = [dev(a) for a in x]
+    yd = [dev(a) for a in y]
+    plan.project(*xd, dt=1.0, want_p=False)
+    plan.project_backward(*yd, dt=1.0)
+    torch.cuda.synchronize()
+    lhs = sum(float((host(a) * b).sum()) for a, b in zip(xd, y))
+    rhs = sum(float((a * host(b)).sum()) for a, b in zip(x, yd))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0) * 100
+
+
+def test_gradcheck_tiny():
+    F = fsei()
+    spec = W.small_spec(4, 4, 6, PERIODIC, WALL, stretch=2.0)
+    plan = F.Plan.from_spec(spec)
+    r = W.rng(5)
+    u, v, w = (dev(a) for a in W.random_velocity(spec, 5))
+    wts = [dev(r.uniform(0.5, 1.5, spec.shape)) for _ in range(4)]
+
+    def loss(a, b, c):
+        uo, vo, wo, p = F.project(a, b, c, plan, dt=0.5)
+        return (wts[0] * uo * uo).sum() + (wts[1] * vo * vo).sum() + (wts[2] * wo * wo).sum() + (wts[3] * p).sum()
+
+    for t in (u, v, w):
+        t.requires_grad_(True)
+    mu, mv, mw = W.dead_face_masks(spec)
+    # dead faces do not influence the outputs; perturb only active ones
+    assert torch.autograd.gradcheck(loss, (u, v, w), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=False,
+                                    nondet_tol=1e-12)
+
+
+def test_project_fp32_c1():
+    F = fsei()
+    spec = W.CONFIGS["C1"]
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, W.SEEDS["C1"])
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, _ = run_project(spec, u, v, w, precision=F.PREC_FP32)
+    errs = [rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))]
+    print("C1 fp32 errs", errs)
+    assert max(errs) <= 2e-5
+
+
+@pytest.mark.parametrize("bc", [(WALL, WALL), (PERIODIC, WALL)])
+def test_refine_projection_reaches_fp64(bc):
+    F = fsei()
+    spec = W.small_spec(64, 48, 96, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 9)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6)
+    print("refine info", info, [rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))])
+    assert info["rel_residual"] <= 1e-10
+    f = oracle.divergence(u, v, w, g)
+    assert oracle.rel_residual(f, gp, g) <= 1e-10
+    assert rel(gp, rp) <= 1e-8
+    assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
+
+
+def test_refine_fixed_iterations_and_not_converged():
+    F = fsei()
+    spec = W.small_spec(32, 32, 48, WALL, WALL, lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    u, v, w = W.random_velocity(spec, 10)
+    plan = F.Plan.from_spec(spec, precision=F.PREC_FP32_REFINE, rtol=1e-30, max_iter=1)
+    with pytest.raises(F.FseiError) as e:
+        plan.project(dev(u), dev(v), dev(w), info=True)
+    assert e.value.status == -6
+    plan0 = F.Plan.from_spec(spec, precision=F.PREC_FP32_REFINE, rtol=0.0, max_iter=2)
+    _, info = plan0.project(dev(u), dev(v), dev(w), info=True)
+    assert info["iterations"] == 2 and info["rel_residual"] < 1e-9
