@@ -1,0 +1,236 @@
+"""Benchmark: pressure-projection solves/s on the 512 x 512 x 768 stretched grid.
+
+One step = one full projection (divergence + x/y transforms + per-mode z
+tridiagonals + inverse transforms + gradient correction) of one provisional
+velocity field that is already resident in HBM.  Each timed step projects its
+own copy of the input (the projection works in place), so no copy runs inside
+the timed region.  Both precision modes are measured in the same run:
+
+  * fp32_refine : FP32 transforms/tridiagonals (lowest-mode lines in FP64),
+                  FP64 residual, correction solves to ||r||/||f|| <= 1e-10
+                  (the mode this workload is specified with; reported as value)
+  * fp64        : every step in FP64
+
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
+
+# Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:
+# every operand read once, every result written once).
+BYTES_PER_CELL = {
+    "fp64": {"xfwd": 32, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "grad": 56},
+    "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 12, "resid_xfwd": 20,
+                    "xinv_acc": 20, "grad": 56},
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_mode(mode, spec, u0, v0, w0, steps, warmup, torch, fsei):
+    """Time `steps` projections of resident copies of (u0, v0, w0)."""
+    prec = fsei.PREC_FP64 if mode == "fp64" else fsei.PREC_FP32_REFINE
+    plan = fsei.Plan.from_spec(spec, precision=prec, rtol=1e-10, max_iter=4)
+    ncopy = steps + warmup
+    bufs = [(u0.clone(), v0.clone(), w0.clone()) for _ in range(ncopy)]
+    p = torch.empty_like(u0)
+    torch.cuda.synchronize()
+    infos = []
+    for i in range(warmup):
+        _, info = plan.project(*bufs[i], p=p, info=True)
+        infos.append(info)
+    torch.cuda.synchronize()
+    plan.reset_timing()
+    plan.set_timing(True)
+    # refine mode reads one residual norm per iteration back to the host;
+    # FP64 mode runs without any host synchronisation inside the loop
+    t0 = time.perf_counter()
+    for i in range(warmup, ncopy):
+        if mode == "fp64":
+            plan.project(*bufs[i], p=p)
+        else:
+            _, info = plan.project(*bufs[i], p=p, info=True)
+            infos.append(info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_timing(False)
+    ktimes = plan.kernel_times()
+    # check the last output: divergence of the projected field, V-mean of p
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": ktimes}
+    res["last_info"] = infos[-1] if infos else None
+    u, v, w = bufs[-1]
+    res["div_check"] = float(divergence_max(u, v, w, spec, torch))
+    del bufs
+    torch.cuda.empty_cache()
+    return res, plan
+
+
+def divergence_max(u, v, w, spec, torch):
+    """max |D u| of the projected field, relative to max |D u*| scale 1 (GPU,
+    torch ops; a property check, not part of the timed path)."""
+    zc = torch.tensor(spec.zc(), dtype=torch.float64, device=u.device)
+    dz = (zc[1:] - zc[:-1]).view(-1, 1, 1)
+    uh = torch.roll(u, -1, 2)
+    if spec.bcx == 1:
+        uh[:, :, -1] = 0
+        u = u.clone()
+        u[:, :, 0] = 0
+    vh = torch.roll(v, -1, 1)
+    if spec.bcy == 1:
+        vh[:, -1, :] = 0
+        v = v.clone()
+        v[:, 0, :] = 0
+    wh = torch.roll(w, -1, 0)
+    wh[-1] = 0
+    w = w.clone()
+    w[0] = 0
+    d = (uh - u) / spec.dx + (vh - v) / spec.dy + (wh - w) / dz
+    return d.abs().max().item()
+
+
+def roofline_for(mode, res, ncells):
+    """Dominant kernel (largest total time) and its achieved algorithmic
+    bandwidth over the timed region."""
+    kt = res["kernels"]
+    bpc = BYTES_PER_CELL[mode]
+    name = max((k for k in kt if k in bpc), key=lambda k: kt[k][0])
+    total_ms, n = kt[name]
+    avg_s = total_ms / n / 1e3
+    bytes_per_launch = bpc[name] * ncells
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+
+def mode_summary(mode, res, ncells, steps):
+    kt = res["kernels"]
+    bpc = BYTES_PER_CELL[mode]
+    sec = res["ms_per_step"] / 1e3
+    # algorithmic bytes per step from the launches actually made
+    bytes_step = sum(bpc.get(k, 0) * ncells * n for k, (ms, n) in kt.items()) / steps
+    out = {
+        "solves_per_s": round(1.0 / sec, 3),
+        "gpts_per_s": round(ncells / sec / 1e9, 3),
+        "ms_per_step": round(res["ms_per_step"], 4),
+        "model_bytes_per_step_GB": round(bytes_step / 1e9, 3),
+        "hbm_frac_of_peak": round(bytes_step / sec / 1e9 / PEAK_HBM_GBS, 4),
+        "kernel_ms_per_step": {k: round(ms / steps, 4) for k, (ms, n) in kt.items()},
+        "max_abs_div_after": res["div_check"],
+    }
+    if res["last_info"]:
+        out["iterations"] = res["last_info"]["iterations"]
+        out["rel_residual"] = res["last_info"]["rel_residual"]
+    return out
+
+
+def cpu_baseline(spec):
+    """The FP64 CPU oracle, timed on a bounded sample of the same workload:
+    the full projection of the bottom 96 of the 768 z-planes of the same grid
+    (same x,y lengths and stretched faces, 1/8 of the cells), scaled to
+    solves/s of the whole grid."""
+    import oracle
+    from paper_2103_15187_amd import workloads as W
+    nzs = 96
+    sub = W.GridSpec(spec.nx, spec.ny, nzs, spec.bcx, spec.bcy, spec.lx, spec.ly, spec.lz, spec.stretch)
+    zc = spec.zc()[: nzs + 1]
+    g = oracle.Grid(sub.nx, sub.ny, nzs, sub.bcx, sub.bcy, sub.dx, sub.dy, zc)
+    u, v, w = W.random_velocity(sub, W.SEEDS["C3"])
+    threads = None
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 0) for i in threadpool_info()), default=None)
+    except Exception:
+        pass
+    t0 = time.perf_counter()
+    oracle.project(u, v, w, g)
+    dt = time.perf_counter() - t0
+    frac = nzs / spec.nz
+    return {"value": round(frac / dt, 6), "unit": "solves/s", "cores": threads or len(os.sched_getaffinity(0)),
+            "kind": "oracle", "sample": f"full FP64 oracle projection of the bottom {nzs} of {spec.nz} z-planes "
+            f"({spec.nx}x{spec.ny}x{nzs}, same grid), {dt:.2f} s, scaled by {spec.nz // nzs}",
+            "seconds_for_sample": round(dt, 3), "host_cores": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="C3")
+    ap.add_argument("--modes", default="fp32_refine,fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs the projection on one GPU only; multi-GPU runs are not supported "
+              "(the slab decomposition is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps + args.warmup > 30:
+        print("bench.py: steps + warmup <= 30 (each step keeps its own resident input copy)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2103_15187_amd import fsei, workloads as W
+    spec = W.CONFIGS[args.config]
+    log(f"[bench] generating {args.config} input {spec.shape}")
+    if args.config == "C3":
+        u, v, w = W.c3_velocity(spec, W.SEEDS["C3"])
+    else:
+        u, v, w = W.random_velocity(spec, W.SEEDS.get(args.config, 1))
+    dev = torch.device("cuda:0")
+    u0, v0, w0 = (torch.from_numpy(a).to(dev) for a in (u, v, w))
+    del u, v, w
+    ncells = spec.ncells
+    modes = [m for m in args.modes.split(",") if m]
+    results = {}
+    for m in modes:
+        log(f"[bench] mode {m}: warmup {args.warmup}, steps {args.steps}")
+        res, _ = gpu_mode(m, spec, u0, v0, w0, args.steps, args.warmup, torch, fsei)
+        results[m] = res
+        log(f"[bench] mode {m}: {res['ms_per_step']:.3f} ms/step")
+    head = modes[0]
+    hres = results[head]
+    line = {
+        "metric": "Poisson-projection solves/s & Gpts/s at 512^2x768; FP32+refine vs FP64, %HBM peak",
+        "value": round(1e3 / hres["ms_per_step"], 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(hres["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "fp32_refine" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {spec.nx}x{spec.ny}x{spec.nz} cells, bc x/y "
+                   f"{'wall' if spec.bcx else 'periodic'}/{'wall' if spec.bcy else 'periodic'}, z walls "
+                   f"tanh {spec.stretch}, u* N(0,1) + Gaussian jet, dt=1; value = {head}",
+                   "grid": [spec.nx, spec.ny, spec.nz], "mode": head},
+        "roofline": roofline_for(head, hres, ncells),
+        "modes": {m: mode_summary(m, results[m], ncells, args.steps) for m in modes},
+        "gpts_per_s": round(ncells * 1e3 / hres["ms_per_step"] / 1e9, 3),
+    }
+    for m in modes:
+        line["modes"][m]["roofline"] = roofline_for(m, results[m], ncells)
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle on a bounded sample)")
+        line["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

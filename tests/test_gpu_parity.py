@@ -103,7 +103,7 @@ def test_project_fp64_c1():
 @pytest.mark.parametrize("bc", BCS)
 def test_poisson_solve_incompatible_rhs_and_in_place(bc):
     F = fsei()
-    spec = W.small_spec(24, 20, 28, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
+    spec = W.small_spec(24, 18, 28, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
     g = grid_of(spec)
     f = W.rng(3).standard_normal(spec.shape) + 0.25
     rp, rinfo = oracle.poisson_solve(f, g, return_info=True)
@@ -121,7 +121,7 @@ def test_poisson_solve_incompatible_rhs_and_in_place(bc):
 @pytest.mark.parametrize("with_gp", [False, True])
 def test_backward_fp64_matches_oracle_adjoint(bc, with_gp):
     F = fsei()
-    spec = W.small_spec(12, 10, 14, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
+    spec = W.small_spec(12, 9, 14, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
     g = grid_of(spec)
     r = W.rng(17)
     gu, gv, gw = (r.standard_normal(spec.shape) for _ in range(3))
