@@ -174,6 +174,9 @@ def main():
     ap.add_argument("--config", default="C3")
     ap.add_argument("--modes", default="fp32_refine,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run torch.neg over one field (a plain streaming kernel of known size: "
+                         "reads and writes 8 B per cell) to calibrate hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs the projection on one GPU only; multi-GPU runs are not supported "
@@ -194,6 +197,11 @@ def main():
     u0, v0, w0 = (torch.from_numpy(a).to(dev) for a in (u, v, w))
     del u, v, w
     ncells = spec.ncells
+    if args.calib:
+        tmp = torch.empty_like(u0)
+        torch.neg(u0, out=tmp)
+        torch.cuda.synchronize()
+        del tmp
     modes = [m for m in args.modes.split(",") if m]
     results = {}
     for m in modes:

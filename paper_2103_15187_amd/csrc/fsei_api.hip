@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 #include <vector>
 
@@ -15,8 +16,7 @@ using namespace fsei::dev;
 
 namespace {
 
-constexpr int kThrX = 256;
-constexpr int kEmaxY = 2048, kThrY = 256;
+
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
@@ -104,8 +104,8 @@ void* field2(const fsei_plan* p) { return (char*)p->ws + p->ws_field2; }
 void* field3(const fsei_plan* p) { return (char*)p->ws + p->ws_field3; }
 int* zlist(const fsei_plan* p) { return reinterpret_cast<int*>((char*)p->ws + p->ws_list); }
 
-int nseq_x(const fsei_plan* p) { return std::max(1, kEmaxX / p->nx); }
-int nseq_y(const fsei_plan* p) { return std::max(1, kEmaxY / p->ny); }
+int nseq_x(const fsei_plan* p) { return x_nseq(p->nx); }
+
 long xblocks(const fsei_plan* p) {
     const long nl = 2L * nseq_x(p);
     return ((long)p->ny * p->nz + nl - 1) / nl;
@@ -129,8 +129,12 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
     a.tws = tab<TO>(p, T_TWX_S);
     a.dctc = tab<TO>(p, T_DCTX_C);
     a.dcts = tab<TO>(p, T_DCTX_S);
+    const size_t dyn = 2 * p->nx * sizeof(TO);
     Timed t(p, slot);
-    hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, kEmaxX, kThrX>), dim3((unsigned)xblocks(p)), dim3(kThrX), 0, S(p), a);
+    if (p->nx == 512)
+        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
+    else
+        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
 }
 
 template <typename T, typename TP, int EPI>
@@ -148,10 +152,39 @@ void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot) {
     a.tws = tab<T>(p, T_TWX_S);
     a.dctc = tab<T>(p, T_DCTX_C);
     a.dcts = tab<T>(p, T_DCTX_S);
+    const size_t dyn = 2 * p->nx * sizeof(T);
     Timed t(p, slot);
-    hipLaunchKernelGGL((k_xinv<T, TP, EPI, kEmaxX, kThrX>), dim3((unsigned)xblocks(p)), dim3(kThrX), 0, S(p), a);
+    if (p->nx == 512)
+        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
+    else
+        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
 }
 
+template <typename T, int EMAX, int NTHR>
+void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
+    a.nseq = std::max(1, std::min(tile_nseq(EMAX, p->ny), (p->nx + 1) / 2));
+    const int tx = 2 * a.nseq;
+    a.ntile = (p->nx + tx - 1) / tx;
+    const unsigned nb = (unsigned)(a.ntile * p->nz);
+    const size_t dyn = 2 * p->ny * sizeof(T);
+    const bool n512 = p->ny == 512;
+    if (inverse) {
+        Timed t(p, K_YINV);
+        if (n512)
+            hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+        else
+            hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, 0>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+    } else {
+        Timed t(p, K_YFWD);
+        if (n512)
+            hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+        else
+            hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 0>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+    }
+}
+
+// y tiles: the workgroup's LDS holds enough columns that every row segment
+// it loads or stores covers 128 B (16 doubles / 32 floats) when ny allows
 template <typename T>
 void launch_y(fsei_plan* p, T* data, bool inverse) {
     YArgs<T> a{};
@@ -159,23 +192,39 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
     a.ny = p->ny;
     a.nz = p->nz;
     a.bcy = p->bcy;
-    a.nseq = nseq_y(p);
-    const int tx = 2 * a.nseq;
-    a.ntile = (p->nx + tx - 1) / tx;
     a.fp = p->fy;
     a.data = data;
     a.twc = tab<T>(p, T_TWY_C);
     a.tws = tab<T>(p, T_TWY_S);
     a.dctc = tab<T>(p, T_DCTY_C);
     a.dcts = tab<T>(p, T_DCTY_S);
-    const unsigned nb = (unsigned)(a.ntile * p->nz);
-    if (inverse) {
-        Timed t(p, K_YINV);
-        hipLaunchKernelGGL((k_yinv<T, kEmaxY, kThrY>), dim3(nb), dim3(kThrY), 0, S(p), a);
-    } else {
-        Timed t(p, K_YFWD);
-        hipLaunchKernelGGL((k_yfwd<T, kEmaxY, kThrY>), dim3(nb), dim3(kThrY), 0, S(p), a);
-    }
+    // complex elements of a tile whose row segments are 128 B; the tile
+    // (2 arrays, padded) plus the 2 ny twiddles must fit in the 160 KB of LDS
+    const long want = (long)(64 / sizeof(T)) * p->ny;
+    auto fits = [&](long emax) {
+        return 2L * lds_elems((int)emax) * (long)sizeof(T) + 2L * p->ny * (long)sizeof(T) <= 160L * 1024;
+    };
+    if (want <= 2048)
+        launch_y_cfg<T, 2048, 256>(p, a, inverse);
+    else if (want <= 4096 || !fits(8192))
+        launch_y_cfg<T, 4096, 512>(p, a, inverse);
+    else if (sizeof(T) == 8 || want <= 8192 || !fits(16384))
+        launch_y_cfg<T, 8192, 1024>(p, a, inverse);
+    else
+        launch_y_cfg<T, (sizeof(T) == 8 ? 8192 : 16384), 1024>(p, a, inverse);
+}
+
+// Tiling of the z solve: 0 = 16 (FP64) / 32 (FP32) adjacent modes per
+// workgroup with at most 32 chunks per line; 1 = half as many modes with up
+// to 64 chunks (shorter chunks, fewer registers); 2 (FP64) = 16 modes with up
+// to 64 chunks in 1024-thread workgroups.  All tilings do the same work; the
+// environment variable FSEI_Z_CFG selects one for measurement.
+int zcfg() {
+    static int v = [] {
+        const char* e = getenv("FSEI_Z_CFG");
+        return e ? atoi(e) : 0;
+    }();
+    return v;
 }
 
 // chunking of the z lines: P chunks of exactly L rows (L one of the compiled
@@ -235,7 +284,16 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         ZArgs<double, double> a = zargs<double, double>(p, data, transposed);
         a.sigma_thr = 0.0;
         int L, P;
-        if (choose_chunks(nz, 32, &L, &P)) {
+        const int cfg = zcfg();
+        if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z_dispatch<double, double, 8, 512, false>(p, a, dim3((p->nx + 7) / 8, p->ny), K_ZSOLVE);
+        } else if (cfg == 2 && choose_chunks(nz, 64, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z_dispatch<double, double, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
+        } else if (choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
             z_dispatch<double, double, 16, 512, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
@@ -249,7 +307,11 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
         a.sigma_thr = (float)p->sigma_thr;
         int L, P;
-        if (choose_chunks(nz, 32, &L, &P)) {
+        if (zcfg() == 1 && choose_chunks(nz, 64, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z_dispatch<float, float, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
+        } else if (choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
             z_dispatch<float, float, 32, 1024, false>(p, a, dim3((p->nx + 31) / 32, p->ny), K_ZSOLVE);
@@ -316,7 +378,7 @@ void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoin
         a.gk = tab<TIO>(p, T_GAM_ADJ);
     }
     Timed t(p, K_GRAD);
-    hipLaunchKernelGGL((k_grad<TIO, TP>), dim3((p->nx + 255) / 256, p->ny, p->nz), dim3(256), 0, S(p), a);
+    hipLaunchKernelGGL((k_grad<TIO, TP>), dim3((unsigned)((long)p->ny * p->nz)), dim3(256), 0, S(p), a);
 }
 
 template <typename TI, typename TO>

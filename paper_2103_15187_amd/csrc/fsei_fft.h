@@ -1,13 +1,19 @@
 // Batched mixed-radix (8/4/3/2) Stockham FFT in LDS for gfx950.
 //
-// A workgroup transforms `nseq` complex sequences of length N that sit in LDS
-// as split real/imaginary arrays (sequence s, element n at logical index
-// s*N + n).  Each radix-R stage reads R inputs at stride N/R, applies the
-// twiddles exp(SIGN 2 pi i t / N), does a length-R DFT in registers and writes
-// the outputs to their self-sorting positions, so the result is in natural
-// order without a bit-reversal pass.  A stage is done in place: every thread
-// first gathers all of its butterflies into registers, then the workgroup
-// synchronises, then every thread scatters.
+// A workgroup transforms `nseq` complex sequences of length N held in LDS as
+// split real/imaginary arrays.  Element n of sequence s sits at
+//     s * SP + n + n / 16,      SP = N + N / 16 + 1,
+// i.e. one pad slot every 16 elements (breaks the power-of-two strides of a
+// stage's scatter) and an odd stride between sequences (threads that walk
+// across sequences at a fixed n hit different banks).  Each radix-R stage
+// reads R inputs at stride N/R, applies the twiddles exp(SIGN 2 pi i t / N),
+// does a length-R DFT in registers and writes the outputs to their
+// self-sorting positions, so the result is in natural order without a
+// bit-reversal pass.  A stage is done in place: every thread gathers all of
+// its butterflies into registers, the workgroup synchronises, then scatters.
+//
+// When the length is a compile-time constant (NF > 0) the stage loop is
+// unrolled with constant radices and strides, so no integer division remains.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,10 +23,8 @@
 namespace fsei {
 namespace dev {
 
-// LDS index with one pad slot every 16 elements (breaks the power-of-two
-// strides of the scatter into distinct banks).
-__device__ __forceinline__ int lp(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_elems(int e) { return e + (e >> 4) + 1; }
+// seq_stride, lds_elems and tile_nseq (the tile geometry) live in fsei_plan.h
+__device__ __forceinline__ int li(int s, int n, int SP) { return s * SP + n + (n >> 4); }
 
 template <typename T>
 __device__ __forceinline__ void cmul(T& ar, T& ai, T br, T bi) {
@@ -116,9 +120,10 @@ __device__ __forceinline__ void dftR(T* xr, T* xi) {
 }
 
 // One Stockham stage of radix R over all nseq sequences.  MAXB bounds the
-// butterflies per thread: nseq*N/R <= MAXB*blockDim.x.
-template <typename T, int R, int MAXB, int SIGN>
-__device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im, int N, int nseq, int Ns,
+// butterflies per thread: nseq*N/R <= MAXB*blockDim.x.  N and Ns are
+// compile-time constants when the caller's are.
+template <typename T, int R, int MAXB, int SIGN, int NTHR>
+__device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im, int N, int SP, int nseq, int Ns,
                                           const T* __restrict__ twc, const T* __restrict__ tws) {
     const int NR = N / R;
     const int nb = nseq * NR;
@@ -127,17 +132,17 @@ __device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im
     int dst[MAXB];
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
-        const int w = threadIdx.x + b * blockDim.x;
+        const int w = threadIdx.x + b * NTHR;
         dst[b] = -1;
         if (w < nb) {
             const int s = w / NR;
             const int j = w - s * NR;
             const int k = j % Ns;
-            const int base = s * N;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                vr[b][r] = re[lp(base + j + r * NR)];
-                vi[b][r] = im[lp(base + j + r * NR)];
+                const int o = li(s, j + r * NR, SP);
+                vr[b][r] = re[o];
+                vi[b][r] = im[o];
             }
             if (Ns > 1) {
 #pragma unroll
@@ -147,17 +152,20 @@ __device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im
                 }
             }
             dftR<T, R, SIGN>(vr[b], vi[b]);
-            dst[b] = base + (j - k) * R + k;
+            dst[b] = s * (1 << 20) + (j - k) * R + k;   // (sequence, position) packed
         }
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < MAXB; ++b) {
         if (dst[b] >= 0) {
+            const int s = dst[b] >> 20;
+            const int pos = dst[b] & ((1 << 20) - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                re[lp(dst[b] + r * Ns)] = vr[b][r];
-                im[lp(dst[b] + r * Ns)] = vi[b][r];
+                const int o = li(s, pos + r * Ns, SP);
+                re[o] = vr[b][r];
+                im[o] = vi[b][r];
             }
         }
     }
@@ -166,22 +174,64 @@ __device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im
 
 __host__ __device__ constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// radix schedule shared with the host plan: 8s, then a 4 or a 2, then 3s
+__host__ __device__ constexpr int pow2_part(int n) { return (n % 3 == 0) ? pow2_part(n / 3) : n; }
+__host__ __device__ constexpr int num_stages(int n) {
+    int m = pow2_part(n), c = 0;
+    int r3 = 0;
+    for (int t = n; t % 3 == 0; t /= 3) ++r3;
+    while (m >= 8 && m % 8 == 0) {
+        m /= 8;
+        ++c;
+    }
+    if (m == 4 || m == 2) ++c;
+    return c + r3;
+}
+__host__ __device__ constexpr int stage_radix(int n, int st) {
+    int m = pow2_part(n), c = 0;
+    while (m >= 8 && m % 8 == 0) {
+        if (c == st) return 8;
+        m /= 8;
+        ++c;
+    }
+    if (m == 4 || m == 2) {
+        if (c == st) return m;
+        ++c;
+    }
+    return 3;
+}
+
+template <typename T, int EMAX, int NTHR, int SIGN, int NF, int ST, int NS>
+__device__ __forceinline__ void fft_fixed(T* re, T* im, int nseq, const T* __restrict__ twc,
+                                          const T* __restrict__ tws) {
+    if constexpr (ST < num_stages(NF)) {
+        constexpr int R = stage_radix(NF, ST);
+        fft_stage<T, R, cdiv(EMAX, NTHR * R), SIGN, NTHR>(re, im, NF, seq_stride(NF), nseq, NS, twc, tws);
+        fft_fixed<T, EMAX, NTHR, SIGN, NF, ST + 1, NS * R>(re, im, nseq, twc, tws);
+    }
+}
+
 // Full transform of nseq sequences (nseq*N <= EMAX) with NTHR threads.
-template <typename T, int EMAX, int NTHR, int SIGN>
-__device__ void fft_lds(T* re, T* im, int N, int nseq, const FftPlan& pl, const T* __restrict__ twc,
-                        const T* __restrict__ tws) {
-    int Ns = 1;
-    for (int st = 0; st < pl.nstages; ++st) {
-        const int R = pl.radix[st];
-        if (R == 8)
-            fft_stage<T, 8, cdiv(EMAX, NTHR * 8), SIGN>(re, im, N, nseq, Ns, twc, tws);
-        else if (R == 4)
-            fft_stage<T, 4, cdiv(EMAX, NTHR * 4), SIGN>(re, im, N, nseq, Ns, twc, tws);
-        else if (R == 2)
-            fft_stage<T, 2, cdiv(EMAX, NTHR * 2), SIGN>(re, im, N, nseq, Ns, twc, tws);
-        else
-            fft_stage<T, 3, cdiv(EMAX, NTHR * 3), SIGN>(re, im, N, nseq, Ns, twc, tws);
-        Ns *= R;
+template <typename T, int EMAX, int NTHR, int SIGN, int NF>
+__device__ __forceinline__ void fft_lds(T* re, T* im, int N, int nseq, const FftPlan& pl,
+                                        const T* __restrict__ twc, const T* __restrict__ tws) {
+    if constexpr (NF > 0) {
+        fft_fixed<T, EMAX, NTHR, SIGN, NF, 0, 1>(re, im, nseq, twc, tws);
+    } else {
+        const int SP = seq_stride(N);
+        int Ns = 1;
+        for (int st = 0; st < pl.nstages; ++st) {
+            const int R = pl.radix[st];
+            if (R == 8)
+                fft_stage<T, 8, cdiv(EMAX, NTHR * 8), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+            else if (R == 4)
+                fft_stage<T, 4, cdiv(EMAX, NTHR * 4), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+            else if (R == 2)
+                fft_stage<T, 2, cdiv(EMAX, NTHR * 2), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+            else
+                fft_stage<T, 3, cdiv(EMAX, NTHR * 3), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+            Ns *= R;
+        }
     }
 }
 

@@ -56,7 +56,7 @@ void compute_layout(fsei_plan_impl* p) {
             }
     }
     p->nlist = (int)p->list_host.size();
-    const long nseq = std::max(1, kEmaxX / p->nx);
+    const long nseq = x_nseq(p->nx);
     p->n_partials = (size_t)(((long)p->ny * p->nz + 2 * nseq - 1) / (2 * nseq));
 
     size_t off = 0;

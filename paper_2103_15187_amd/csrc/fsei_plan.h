@@ -15,7 +15,20 @@ constexpr int kMaxStages = 16;
 constexpr int kMaxN = 2048;     // longest x/y transform
 constexpr int kMaxNz = 2048;    // longest z line
 constexpr size_t kAlign = 256;
-constexpr int kEmaxX = 2048;   // complex elements per x-transform workgroup
+// complex elements per x-transform workgroup (and 8 per thread): small tiles
+// keep several workgroups resident per CU so loads, LDS transforms and
+// stores of different workgroups overlap
+inline int x_emax(int) { return 2048; }
+
+// LDS tile geometry shared by the host (launch sizes) and the kernels:
+// sequence s of length N starts at s * seq_stride(N); one array of a tile of
+// emax complex elements holds lds_elems(emax) slots.
+constexpr int seq_stride(int N) { return N + (N >> 4) + 1; }
+constexpr int lds_elems(int emax) { return emax + (emax >> 4) + 16; }
+constexpr int tile_nseq(int emax, int N) {
+    return (emax / N < lds_elems(emax) / seq_stride(N)) ? emax / N : lds_elems(emax) / seq_stride(N);
+}
+inline int x_nseq(int nx) { return tile_nseq(x_emax(nx), nx) > 0 ? tile_nseq(x_emax(nx), nx) : 1; }
 
 // Radix schedule of one complex FFT length (radices 8, 4, 2, 3).
 struct FftPlan {

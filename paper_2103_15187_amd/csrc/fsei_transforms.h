@@ -1,0 +1,505 @@
+// Transform kernels of the pressure projection for gfx950 (MI355X): the x
+// transforms (fused with the divergence / transposed-gradient / residual
+// stencils on the way in and the pressure write or accumulation on the way
+// out) and the y transforms.
+//
+// Transforms (paper, Program summary: FFTW in the homogeneous directions):
+// two real lines a, b travel as one complex sequence z = a + i b through a
+// length-N FFT.  Walls use the DCT-II basis cos(pi q (i+1/2)/N), computed from
+// the even/odd reordering v_n = x_{2n}, v_{N-1-n} = x_{2n+1} and a post-twiddle
+// exp(-i pi q / 2N) (Makhoul's method); periodic directions use the real DFT
+// in half-complex layout (real parts at rows 0..N/2, imaginary parts of mode
+// m at row N-m).  Both inverses are unnormalised (they return N times the
+// input); the z solve folds in the factor 1/(nx ny).
+//
+// Every kernel has an optional compile-time length NF (0 = taken from the
+// arguments): with NF fixed the FFT stages and all index arithmetic fold to
+// constants.  Tile loops have compile-time trip counts and are unrolled, so
+// a thread issues all loads of a batch before the first wait; addresses are
+// 32-bit offsets from per-workgroup base pointers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fsei_fft.h"
+#include "fsei_plan.h"
+
+namespace fsei {
+namespace dev {
+
+// position of element i in the even/odd reordered sequence (walls)
+__device__ __forceinline__ int mk_pos(int i, int N) { return (i & 1) ? N - 1 - (i >> 1) : (i >> 1); }
+
+// Workgroups are handed to the 8 XCDs of the chip round-robin (workgroup i
+// runs on XCD i % 8), and each XCD has its own L2.  This bijection of
+// [0, n) gives XCD x a contiguous run of logical blocks, so blocks that
+// touch neighbouring rows and planes (stencil halos) share an L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ long xcd_remap(long i, long n) {
+    const long q = n / kXcds, r = n % kXcds;
+    const long x = i % kXcds, t = i / kXcds;
+    return x * q + (x < r ? x : r) + t;
+}
+
+// deterministic block sum of two values (result valid in thread 0)
+template <int NTHR>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_down(a, off, 64);
+        b += __shfl_down(b, off, 64);
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        sh[2 * wid] = a;
+        sh[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sb = 0.0;
+        for (int w = 0; w < NTHR / 64; ++w) {
+            sa += sh[2 * w];
+            sb += sh[2 * w + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+    __syncthreads();
+}
+
+// copies the length-N twiddle table exp(2 pi i t / N) into LDS (2 N values);
+// visible after the next barrier
+template <typename T, int NTHR>
+__device__ __forceinline__ T* lds_twiddles(const T* __restrict__ twc, const T* __restrict__ tws, int N) {
+    extern __shared__ __align__(16) unsigned char dyn_lds[];
+    T* twl = reinterpret_cast<T*>(dyn_lds);
+    for (int t = threadIdx.x; t < N; t += NTHR) {
+        twl[t] = twc[t];
+        twl[N + t] = tws[t];
+    }
+    return twl;
+}
+
+// forward post-processing of pair s: the two real outputs at row m
+template <typename T>
+__device__ __forceinline__ void post_fwd(const T* re, const T* im, int s, int SP, int N, int m, int bc,
+                                         const T* __restrict__ dctc, const T* __restrict__ dcts, T& xa,
+                                         T& xb) {
+    const T half = (T)0.5;
+    if (bc == FSEI_BC_WALL) {
+        const int mm = (m == 0) ? 0 : N - m;
+        const T zr = re[li(s, m, SP)], zi = im[li(s, m, SP)];
+        const T cr = re[li(s, mm, SP)], ci = im[li(s, mm, SP)];
+        const T ar = (zr + cr) * half, ai = (zi - ci) * half;
+        const T br = (zi + ci) * half, bi = (cr - zr) * half;
+        const T wr = dctc[m], wi = -dcts[m];
+        xa = wr * ar - wi * ai;
+        xb = wr * br - wi * bi;
+    } else {
+        if (2 * m <= N) {
+            const int mm = (m == 0) ? 0 : N - m;
+            xa = (re[li(s, m, SP)] + re[li(s, mm, SP)]) * half;
+            xb = (im[li(s, m, SP)] + im[li(s, mm, SP)]) * half;
+        } else {
+            const int q = N - m;
+            xa = (im[li(s, q, SP)] - im[li(s, m, SP)]) * half;
+            xb = (re[li(s, m, SP)] - re[li(s, q, SP)]) * half;
+        }
+    }
+}
+
+// inverse pre-processing: complex input Z[m] of the pair from the rows m and
+// N-m of the two transformed lines
+template <typename T>
+__device__ __forceinline__ void pre_inv(int N, int m, int bc, T xam, T xanm, T xbm, T xbnm,
+                                        const T* __restrict__ dctc, const T* __restrict__ dcts, T& zr, T& zi) {
+    if (bc == FSEI_BC_WALL) {
+        if (m == 0) {
+            xanm = (T)0;
+            xbnm = (T)0;
+        }
+        const T c = dctc[m], s = dcts[m];
+        const T var = c * xam + s * xanm, vai = s * xam - c * xanm;
+        const T vbr = c * xbm + s * xbnm, vbi = s * xbm - c * xbnm;
+        zr = var - vbi;
+        zi = vai + vbr;
+    } else {
+        T ra, ia, rb, ib;
+        if (2 * m <= N) {
+            ra = xam;
+            rb = xbm;
+            const bool hasim = (m != 0) && (2 * m != N);
+            ia = hasim ? xanm : (T)0;
+            ib = hasim ? xbnm : (T)0;
+        } else {
+            ra = xanm;
+            rb = xbnm;
+            ia = -xam;
+            ib = -xbm;
+        }
+        zr = ra - ib;
+        zi = ia + rb;
+    }
+}
+
+// (k, j) of row j0 + l of plane k0 (rows wrap into the following planes)
+__device__ __forceinline__ void row_kj(int k0, int j0, int l, int ny, int& k, int& j) {
+    j = j0 + l;
+    k = k0;
+    if (j >= ny) {
+        k += j / ny;
+        j -= (j / ny) * ny;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x forward: prologue (divergence / transposed gradient / residual / copy)
+// fused with the forward x transform
+// ---------------------------------------------------------------------------
+enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3 };
+
+template <typename TI, typename TO>
+struct XFwdArgs {
+    int nx, ny, nz, bcx, bcy, nseq;
+    FftPlan fp;
+    // prologue inputs
+    const TI* u;
+    const TI* v;
+    const TI* w;
+    const TI* gp;       // adjoint: dLoss/dp or null
+    const double* f;    // COPY (double input) and RESID
+    const double* p;    // RESID
+    TI alpha, beta, idx, idy;
+    const TI* zeta;     // coefficient of w_{k+1}
+    const TI* eta;      // coefficient of w_k
+    double idx2, idy2;  // RESID
+    const double* za;   // RESID
+    const double* zc;   // RESID
+    const double* scal; // RESID: scal[0] = removed mean
+    // outputs
+    TO* out;
+    double* out_f;      // optional FP64 copy of the prologue value
+    double* partials;   // optional per-block (sum v^2, sum v)
+    const TO* twc;
+    const TO* tws;
+    const TO* dctc;
+    const TO* dcts;
+};
+
+// The stencil value at cell (k, j, i); `o` is the cell's offset from the
+// workgroup base `base` (first cell of its first row), so all accesses are
+// 32-bit offsets from base pointers.
+template <typename TI, typename TO, int PRO>
+__device__ __forceinline__ TI x_prologue(const XFwdArgs<TI, TO>& a, size_t base, int k, int j, int i, int o,
+                                         int N) {
+    const int nx = N, ny = a.ny, nz = a.nz;
+    const int nxy = nx * ny;
+    if constexpr (PRO == PRO_COPY) {
+        return (TI)a.f[base + o];
+    } else if constexpr (PRO == PRO_RESID) {
+        const double* __restrict__ p = a.p + base;
+        const double pc = p[o];
+        double lx = 0.0, ly = 0.0, lz = 0.0;
+        if (i + 1 < nx) lx += p[o + 1] - pc;
+        else if (a.bcx == FSEI_BC_PERIODIC) lx += p[o + 1 - nx] - pc;
+        if (i >= 1) lx += p[o - 1] - pc;
+        else if (a.bcx == FSEI_BC_PERIODIC) lx += p[o + nx - 1] - pc;
+        if (j + 1 < ny) ly += p[o + nx] - pc;
+        else if (a.bcy == FSEI_BC_PERIODIC) ly += p[o - (ny - 1) * nx] - pc;
+        if (j >= 1) ly += p[o - nx] - pc;
+        else if (a.bcy == FSEI_BC_PERIODIC) ly += p[o + (ny - 1) * nx] - pc;
+        if (k + 1 < nz) lz += a.zc[k] * (p[o + nxy] - pc);
+        if (k >= 1) lz += a.za[k] * (p[o - nxy] - pc);
+        const double lap = lx * a.idx2 + ly * a.idy2 + lz;
+        return (TI)((a.f[base + o] - a.scal[0]) - lap);
+    } else {
+        const TI* __restrict__ u = a.u + base;
+        const TI* __restrict__ v = a.v + base;
+        const TI* __restrict__ w = a.w + base;
+        const TI zero = (TI)0;
+        const TI uc = (a.bcx == FSEI_BC_WALL && i == 0) ? zero : u[o];
+        const TI uh = (i + 1 < nx) ? u[o + 1] : ((a.bcx == FSEI_BC_PERIODIC) ? u[o + 1 - nx] : zero);
+        const TI vc = (a.bcy == FSEI_BC_WALL && j == 0) ? zero : v[o];
+        const TI vh = (j + 1 < ny) ? v[o + nx] : ((a.bcy == FSEI_BC_PERIODIC) ? v[o - (ny - 1) * nx] : zero);
+        const TI wc = (k == 0) ? zero : w[o];
+        const TI wh = (k + 1 < nz) ? w[o + nxy] : zero;
+        TI val = (uh - uc) * a.idx + (vh - vc) * a.idy + (a.zeta[k] * wh - a.eta[k] * wc);
+        val *= a.alpha;
+        if constexpr (PRO == PRO_DIV_ADJ) {
+            if (a.gp) val += a.beta * a.gp[base + o];
+        }
+        return val;
+    }
+}
+
+template <typename TI, typename TO, int PRO, int EMAX, int NTHR, int NF>
+__global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
+    __shared__ TO sre[lds_elems(EMAX)];
+    __shared__ TO sim[lds_elems(EMAX)];
+    __shared__ double sred[2 * (NTHR / 64)];
+    const int N = NF > 0 ? NF : a.nx;
+    const int SP = seq_stride(N);
+    const int nl = 2 * a.nseq;
+    const int total = nl * N;
+    const long row0 = xcd_remap(blockIdx.x, gridDim.x) * nl;
+    const long nrows = (long)a.ny * a.nz;
+    const int k0 = (int)(row0 / a.ny);
+    const int j0 = (int)(row0 - (long)k0 * a.ny);
+    const size_t base = (size_t)row0 * N;
+    TO* twl = lds_twiddles<TO, NTHR>(a.twc, a.tws, N);
+    double* __restrict__ out_f = a.out_f;
+    double ss = 0.0, s1 = 0.0;
+    constexpr int PER = 2 * EMAX / NTHR;   // elements per thread, >= total / NTHR
+    constexpr int BAT = (PER % 4 == 0) ? 4 : 1;
+    for (int r0 = 0; r0 < PER; r0 += BAT) {
+        TI val[BAT];
+#pragma unroll
+        for (int r = 0; r < BAT; ++r) {
+            const int e = threadIdx.x + (r0 + r) * NTHR;
+            val[r] = (TI)0;
+            if (e < total) {
+                const int l = e / N;
+                const int i = e - l * N;
+                if (row0 + l < nrows) {
+                    int k, j;
+                    row_kj(k0, j0, l, a.ny, k, j);
+                    val[r] = x_prologue<TI, TO, PRO>(a, base, k, j, i, e, N);
+                }
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < BAT; ++r) {
+            const int e = threadIdx.x + (r0 + r) * NTHR;
+            if (e < total) {
+                const int l = e / N;
+                const int i = e - l * N;
+                if (row0 + l < nrows) {
+                    if (out_f) out_f[base + e] = (double)val[r];
+                    ss += (double)val[r] * (double)val[r];
+                    s1 += (double)val[r];
+                }
+                const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
+                if (l & 1) sim[li(l >> 1, n, SP)] = (TO)val[r];
+                else sre[li(l >> 1, n, SP)] = (TO)val[r];
+            }
+        }
+    }
+    if (a.partials) {
+        block_sum2<NTHR>(ss, s1, sred);
+        if (threadIdx.x == 0) {
+            a.partials[2 * blockIdx.x] = ss;
+            a.partials[2 * blockIdx.x + 1] = s1;
+        }
+    } else {
+        __syncthreads();
+    }
+    if (a.out == nullptr) return;   // norm-only pass (uniform over the block)
+    fft_lds<TO, EMAX, NTHR, -1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
+    TO* __restrict__ out = a.out + base;
+    constexpr int PST = EMAX / NTHR;
+#pragma unroll
+    for (int r = 0; r < PST; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < a.nseq * N) {
+            const int s = e / N;
+            const int m = e - s * N;
+            TO xa, xb;
+            post_fwd<TO>(sre, sim, s, SP, N, m, a.bcx, a.dctc, a.dcts, xa, xb);
+            if (row0 + 2 * s < nrows) out[2 * s * N + m] = xa;
+            if (row0 + 2 * s + 1 < nrows) out[(2 * s + 1) * N + m] = xb;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x inverse: unnormalised inverse x transform of row pairs; writes (STORE)
+// or adds (ACC) the result into the output field
+// ---------------------------------------------------------------------------
+enum { EPI_STORE = 0, EPI_ACC = 1 };
+
+template <typename T, typename TP>
+struct XInvArgs {
+    int nx, ny, nz, bcx, nseq;
+    FftPlan fp;
+    const T* in;
+    TP* out;
+    const T* twc;
+    const T* tws;
+    const T* dctc;
+    const T* dcts;
+};
+
+template <typename T, typename TP, int EPI, int EMAX, int NTHR, int NF>
+__global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
+    __shared__ T sre[lds_elems(EMAX)];
+    __shared__ T sim[lds_elems(EMAX)];
+    const int N = NF > 0 ? NF : a.nx;
+    const int SP = seq_stride(N);
+    const int nl = 2 * a.nseq;
+    const long row0 = xcd_remap(blockIdx.x, gridDim.x) * nl;
+    const long nrows = (long)a.ny * a.nz;
+    const size_t base = (size_t)row0 * N;
+    const T* __restrict__ in = a.in + base;
+    T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
+    constexpr int PLD = EMAX / NTHR;
+#pragma unroll
+    for (int r = 0; r < PLD; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < a.nseq * N) {
+            const int s = e / N;
+            const int m = e - s * N;
+            const int nm = (m == 0) ? 0 : N - m;
+            T xam = 0, xanm = 0, xbm = 0, xbnm = 0;
+            if (row0 + 2 * s < nrows) {
+                xam = in[2 * s * N + m];
+                xanm = in[2 * s * N + nm];
+            }
+            if (row0 + 2 * s + 1 < nrows) {
+                xbm = in[(2 * s + 1) * N + m];
+                xbnm = in[(2 * s + 1) * N + nm];
+            }
+            T zr, zi;
+            pre_inv<T>(N, m, a.bcx, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
+            sre[li(s, m, SP)] = zr;
+            sim[li(s, m, SP)] = zi;
+        }
+    }
+    __syncthreads();
+    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
+    TP* __restrict__ out = a.out + base;
+    constexpr int PST = 2 * EMAX / NTHR;
+#pragma unroll
+    for (int r = 0; r < PST; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < nl * N) {
+            const int l = e / N;
+            const int i = e - l * N;
+            if (row0 + l < nrows) {
+                const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
+                const T val = (l & 1) ? sim[li(l >> 1, n, SP)] : sre[li(l >> 1, n, SP)];
+                if constexpr (EPI == EPI_ACC) out[e] += (TP)val;
+                else out[e] = (TP)val;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y transforms, in place, on tiles of TX = 2*nseq adjacent x-columns of one
+// z-plane (each column pair is one complex sequence)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct YArgs {
+    int nx, ny, nz, bcy, nseq, ntile;
+    FftPlan fp;
+    T* data;
+    const T* twc;
+    const T* tws;
+    const T* dctc;
+    const T* dcts;
+};
+
+template <typename T, int EMAX, int NTHR, int NF>
+__global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
+    __shared__ T sre[lds_elems(EMAX)];
+    __shared__ T sim[lds_elems(EMAX)];
+    const int N = NF > 0 ? NF : a.ny;
+    const int SP = seq_stride(N);
+    const int nx = a.nx;
+    const int TX = 2 * a.nseq;
+    const int k = blockIdx.x / a.ntile;
+    const int tile = blockIdx.x - k * a.ntile;
+    const int i0 = tile * TX;
+    T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
+    T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
+    constexpr int PLD = 2 * EMAX / NTHR;
+    T val[PLD];
+#pragma unroll
+    for (int r = 0; r < PLD; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        const int j = e / TX;
+        const int c = e - j * TX;
+        val[r] = (e < TX * N && i0 + c < nx) ? d[j * nx + c] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < PLD; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < TX * N) {
+            const int j = e / TX;
+            const int c = e - j * TX;
+            const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
+            if (c & 1) sim[li(c >> 1, n, SP)] = val[r];
+            else sre[li(c >> 1, n, SP)] = val[r];
+        }
+    }
+    __syncthreads();
+    fft_lds<T, EMAX, NTHR, -1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
+    constexpr int PST = EMAX / NTHR;
+#pragma unroll
+    for (int r = 0; r < PST; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < a.nseq * N) {
+            const int m = e / a.nseq;
+            const int s = e - m * a.nseq;
+            T xa, xb;
+            post_fwd<T>(sre, sim, s, SP, N, m, a.bcy, a.dctc, a.dcts, xa, xb);
+            if (i0 + 2 * s < nx) d[m * nx + 2 * s] = xa;
+            if (i0 + 2 * s + 1 < nx) d[m * nx + 2 * s + 1] = xb;
+        }
+    }
+}
+
+template <typename T, int EMAX, int NTHR, int NF>
+__global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
+    __shared__ T sre[lds_elems(EMAX)];
+    __shared__ T sim[lds_elems(EMAX)];
+    const int N = NF > 0 ? NF : a.ny;
+    const int SP = seq_stride(N);
+    const int nx = a.nx;
+    const int TX = 2 * a.nseq;
+    const int k = blockIdx.x / a.ntile;
+    const int tile = blockIdx.x - k * a.ntile;
+    const int i0 = tile * TX;
+    T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
+    T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
+    constexpr int PLD = EMAX / NTHR;
+#pragma unroll
+    for (int r = 0; r < PLD; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < a.nseq * N) {
+            const int m = e / a.nseq;
+            const int s = e - m * a.nseq;
+            const int nm = (m == 0) ? 0 : N - m;
+            T xam = 0, xanm = 0, xbm = 0, xbnm = 0;
+            if (i0 + 2 * s < nx) {
+                xam = d[m * nx + 2 * s];
+                xanm = d[nm * nx + 2 * s];
+            }
+            if (i0 + 2 * s + 1 < nx) {
+                xbm = d[m * nx + 2 * s + 1];
+                xbnm = d[nm * nx + 2 * s + 1];
+            }
+            T zr, zi;
+            pre_inv<T>(N, m, a.bcy, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
+            sre[li(s, m, SP)] = zr;
+            sim[li(s, m, SP)] = zi;
+        }
+    }
+    __syncthreads();
+    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
+    constexpr int PST = 2 * EMAX / NTHR;
+#pragma unroll
+    for (int r = 0; r < PST; ++r) {
+        const int e = threadIdx.x + r * NTHR;
+        if (e < TX * N) {
+            const int j = e / TX;
+            const int c = e - j * TX;
+            if (i0 + c < nx) {
+                const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
+                d[j * nx + c] = (c & 1) ? sim[li(c >> 1, n, SP)] : sre[li(c >> 1, n, SP)];
+            }
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace fsei
