@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstdlib>
 #include <type_traits>
 #include <vector>
@@ -20,8 +21,9 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "", "", "", "", ""};
+    "zsolve_fp64_lines", "resid_norm", "", "", "", ""};
 constexpr int K_ZLIST = 10;
+constexpr int K_RESNORM = 11;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -111,6 +113,12 @@ long xblocks(const fsei_plan* p) {
     return ((long)p->ny * p->nz + nl - 1) / nl;
 }
 
+// the fixed-length x kernels (NF = 512) need every tile of rows full and
+// inside one z-plane
+bool x_fixed(const fsei_plan* p) {
+    return p->nx == 512 && nseq_x(p) == tile_nseq(2048, 512) && p->ny % (2 * nseq_x(p)) == 0;
+}
+
 hipStream_t S(const fsei_plan* p) { return (hipStream_t)p->stream; }
 
 // ---------------------------------------------------------------------------
@@ -131,7 +139,7 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
     a.dcts = tab<TO>(p, T_DCTX_S);
     const size_t dyn = 2 * p->nx * sizeof(TO);
     Timed t(p, slot);
-    if (p->nx == 512)
+    if (x_fixed(p))
         hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
     else
         hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
@@ -154,7 +162,7 @@ void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot) {
     a.dcts = tab<T>(p, T_DCTX_S);
     const size_t dyn = 2 * p->nx * sizeof(T);
     Timed t(p, slot);
-    if (p->nx == 512)
+    if (x_fixed(p))
         hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
     else
         hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
@@ -167,19 +175,29 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     a.ntile = (p->nx + tx - 1) / tx;
     const unsigned nb = (unsigned)(a.ntile * p->nz);
     const size_t dyn = 2 * p->ny * sizeof(T);
-    const bool n512 = p->ny == 512;
+    // fixed-length variant: full tiles of the compile-time width, column
+    // pairs addressed as one aligned vector
+    constexpr bool kFix = y_fixed_ok(EMAX, NTHR, 512);
+    const bool fix = kFix && p->ny == 512 && a.nseq == tile_nseq(EMAX, 512) && p->nx % tx == 0 &&
+                     reinterpret_cast<uintptr_t>(a.data) % (2 * sizeof(T)) == 0;
     if (inverse) {
         Timed t(p, K_YINV);
-        if (n512)
-            hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
-        else
-            hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, 0>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+        if constexpr (kFix) {
+            if (fix) {
+                hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, 0>), dim3(nb), dim3(NTHR), dyn, S(p), a);
     } else {
         Timed t(p, K_YFWD);
-        if (n512)
-            hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
-        else
-            hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 0>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+        if constexpr (kFix) {
+            if (fix) {
+                hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 0>), dim3(nb), dim3(NTHR), dyn, S(p), a);
     }
 }
 
@@ -214,10 +232,11 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
         launch_y_cfg<T, (sizeof(T) == 8 ? 8192 : 16384), 1024>(p, a, inverse);
 }
 
-// Tiling of the z solve: 0 = 16 (FP64) / 32 (FP32) adjacent modes per
-// workgroup with at most 32 chunks per line; 1 = half as many modes with up
-// to 64 chunks (shorter chunks, fewer registers); 2 (FP64) = 16 modes with up
-// to 64 chunks in 1024-thread workgroups.  All tilings do the same work; the
+// Tiling of the z solve: 0 = two adjacent modes per lane, 32 (FP64) / 64
+// (FP32) modes per workgroup, at most 32 chunks per line (needs nx even);
+// 1 = 8 (FP64) / 16 (FP32) modes, one per lane, up to 64 chunks; 2 (FP64) =
+// 16 modes, one per lane, up to 64 chunks in 1024-thread workgroups; 3 = two
+// modes per lane, 16 (FP64) / 32 (FP32) modes, up to 64 chunks.  All tilings do the same work; the
 // environment variable FSEI_Z_CFG selects one for measurement.
 int zcfg() {
     static int v = [] {
@@ -256,6 +275,19 @@ void z_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid, int slot) {
     }
 }
 
+template <typename TS, typename TC, int TXL2, int NT>
+void z2_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid) {
+    Timed t(p, K_ZSOLVE);
+    switch (a.L) {
+        case 4: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 4, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 8: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 8, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 12: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 12, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 16: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 16, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 24: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 24, NT>), grid, dim3(NT), 0, S(p), a); break;
+        default: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 32, NT>), grid, dim3(NT), 0, S(p), a); break;
+    }
+}
+
 template <typename TS, typename TC>
 ZArgs<TS, TC> zargs(const fsei_plan* p, TS* data, int transposed) {
     ZArgs<TS, TC> a{};
@@ -285,7 +317,15 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         a.sigma_thr = 0.0;
         int L, P;
         const int cfg = zcfg();
-        if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
+        if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z2_dispatch<double, double, 16, 512>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
+        } else if (cfg == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z2_dispatch<double, double, 8, 512>(p, a, dim3((p->nx / 2 + 7) / 8, p->ny));
+        } else if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
             z_dispatch<double, double, 8, 512, false>(p, a, dim3((p->nx + 7) / 8, p->ny), K_ZSOLVE);
@@ -307,7 +347,15 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
         a.sigma_thr = (float)p->sigma_thr;
         int L, P;
-        if (zcfg() == 1 && choose_chunks(nz, 64, &L, &P)) {
+        if (zcfg() == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z2_dispatch<float, float, 32, 1024>(p, a, dim3((p->nx / 2 + 31) / 32, p->ny));
+        } else if (zcfg() == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            z2_dispatch<float, float, 16, 1024>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
+        } else if (zcfg() == 1 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
             z_dispatch<float, float, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
@@ -424,11 +472,14 @@ fsei_status read_scalars(fsei_plan* p, double* host, int n) {
     return FSEI_OK;
 }
 
-// residual norm^2 (and sum) of the last RESID/xfwd pass into scalars[off..off+1]
-void reduce_partials(fsei_plan* p, int off) {
+// sums of the last xfwd pass with partials (sum v^2, sum v, sum dz_k v) into
+// scalars[off..off+2]; with `vmean`, also scalars[0] = the V-mean of v,
+// sum dz_k v / (nx ny lz)
+void reduce_partials(fsei_plan* p, int off, bool vmean = false) {
     Timed t(p, K_NORM);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, S(p), (const double*)partials(p), (int)xblocks(p),
-                       scalars(p) + off);
+    const double scale = 1.0 / ((double)p->nx * (double)p->ny * p->lz);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, S(p), (const double*)partials(p), (int)xblocks(p),
+                       scalars(p) + off, vmean ? scalars(p) : nullptr, scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,19 +495,24 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     first.out = w32;
     first.out_f = f64;
     first.partials = partials(p);
+    first.dzw = tab<double>(p, T_DZ);
     launch_xfwd<double, float, PRO>(p, first, K_XFWD);
-    reduce_partials(p, 1);   // scalars[1] = sum f^2, scalars[2] = sum f
+    // scalars[5..7] = sum f^2, sum f, sum dz_k f; scalars[0] = V-mean of f in
+    // FP64 (the FP32 zero-mode solve removes its own FP32 mean to stay
+    // compatible, but the residual must use the exact one: a constant left in
+    // the residual is in the null space of L and no correction removes it)
+    reduce_partials(p, 5, true);
     launch_y<float>(p, w32, false);
-    launch_z<float>(p, w32, 0, true);   // scalars[0] = removed V-mean
+    launch_z<float>(p, w32, 0, false);
     launch_y<float>(p, w32, true);
     launch_xinv<float, double, EPI_STORE>(p, w32, p64, K_XINV);
     const double N = (double)p->ncells();
     auto rel_from = [&](const double* h) {
-        // ||f - mean||^2 = sum f^2 - 2 mean sum f + N mean^2
+        // ||f - mean||^2 = sum f^2 - 2 mean sum f + N mean^2; h[1] = sum r^2
         const double mean = h[0];
-        double fn2 = h[1] - 2.0 * mean * h[2] + N * mean * mean;
-        if (fn2 <= 0.0) fn2 = h[1];
-        return (fn2 > 0.0) ? std::sqrt(h[3] / fn2) : 0.0;
+        double fn2 = h[5] - 2.0 * mean * h[6] + N * mean * mean;
+        if (fn2 <= 0.0) fn2 = h[5];
+        return (fn2 > 0.0) ? std::sqrt(h[1] / fn2) : 0.0;
     };
     XFwdArgs<double, float> r{};
     r.f = f64;
@@ -470,35 +526,49 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     int it = 0;
     double rel = -1.0;
     bool converged = false;
-    for (; it < p->max_iter; ++it) {
-        r.out = w32;
-        launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
-        if (p->rtol > 0.0) {
-            reduce_partials(p, 3);
-            double h[5];
-            fsei_status st = read_scalars(p, h, 5);
-            if (st != FSEI_OK) return st;
-            rel = rel_from(h);
-            if (rel <= p->rtol) {
-                converged = true;
-                break;
-            }
-        }
+    bool measured = false;   // rel belongs to the current iterate
+    auto residual_norm = [&]() -> fsei_status {
+        reduce_partials(p, 1);   // scalars[1..3]: sum r^2, sum r, 0
+        double h[8];
+        fsei_status st = read_scalars(p, h, 8);
+        if (st != FSEI_OK) return st;
+        rel = rel_from(h);
+        measured = true;
+        converged = p->rtol > 0.0 && rel <= p->rtol;
+        return FSEI_OK;
+    };
+    // residual of the first solve, transformed for the first correction
+    r.out = w32;
+    launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+    if (p->rtol > 0.0) {
+        fsei_status st = residual_norm();
+        if (st != FSEI_OK) return st;
+    }
+    while (!converged && it < p->max_iter) {
         launch_y<float>(p, w32, false);
         launch_z<float>(p, w32, 0, false);
         launch_y<float>(p, w32, true);
         launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC);
+        ++it;
+        measured = false;
+        if (p->rtol > 0.0) {
+            // convergence check of the corrected iterate: norm only, no transform
+            r.out = nullptr;
+            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
+            fsei_status st = residual_norm();
+            if (st != FSEI_OK) return st;
+            if (converged) break;
+        }
+        if (it < p->max_iter) {
+            r.out = w32;   // residual again, transformed for the next correction
+            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+        }
     }
-    const bool need_final = (p->rtol > 0.0 && !converged) || (info != nullptr && !converged);
-    if (need_final) {
-        r.out = nullptr;   // norm only
-        launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
-        reduce_partials(p, 3);
-        double h[5];
-        fsei_status st = read_scalars(p, h, 5);
+    if (info != nullptr && !measured) {
+        r.out = nullptr;
+        launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
+        fsei_status st = residual_norm();
         if (st != FSEI_OK) return st;
-        rel = rel_from(h);
-        if (p->rtol > 0.0 && rel <= p->rtol) converged = true;
     }
     if (info) {
         double h[1];

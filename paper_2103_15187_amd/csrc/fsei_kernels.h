@@ -226,6 +226,216 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Same solver with two adjacent modes (qx, qx+1) per lane: the global
+// accesses become 16-byte (FP64) / 8-byte (FP32) vectors and a workgroup
+// row segment covers 2*TXL2 modes (256 B), which streams markedly better
+// from HBM than 128-B segments; the two lines' recurrences also interleave.
+// Dense mode only; needs nx even.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+template <typename TS, typename TC, int TXL2, int L, int NT>
+__global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
+    using V = typename Vec2<TS>::type;
+    constexpr int PMAX = NT / TXL2;
+    __shared__ TC sh[4][2 * NT];
+    __shared__ TC ta[PMAX * L], tc[PMAX * L], tb[PMAX * L], tm[PMAX * L], tsi[PMAX * L], tso[PMAX * L];
+    const int nx = a.nx, nz = a.nz, P = a.P;
+    const int npad = P * L;
+    for (int k = threadIdx.x; k < npad; k += NT) {
+        const bool in = k < nz;
+        ta[k] = in ? a.za[k] : (TC)0;
+        tc[k] = in ? a.zc[k] : (TC)0;
+        tb[k] = in ? a.zb0[k] : (TC)1;   // diagonal b0_k + sigma * tm_k
+        tm[k] = in ? (TC)1 : (TC)0;
+        tsi[k] = in ? (a.transposed ? a.scale * a.inv_dz[k] : a.scale) : (TC)0;
+        tso[k] = in ? (a.transposed ? a.dz[k] : (TC)1) : (TC)0;
+    }
+    const int ln = threadIdx.x % TXL2;
+    const int p = threadIdx.x / TXL2;
+    const int qx0 = (blockIdx.x * TXL2 + ln) * 2;
+    const int qy = blockIdx.y;
+    const size_t stride2 = (size_t)nx * a.ny / 2;   // in vectors
+    bool act[2];
+    TC sigma[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int qx = qx0 + h;
+        act[h] = qx < nx;
+        sigma[h] = (TC)-1;
+        if (act[h]) {
+            sigma[h] = a.lamx[qx] + a.lamy[qy];
+            if ((qx == 0 && qy == 0) || fabs(sigma[h]) < a.sigma_thr) act[h] = false;
+            if (!act[h]) sigma[h] = (TC)-1;
+        }
+    }
+    const bool inrange = p < P;
+    const int s0 = inrange ? p * L : 0;
+    const bool anyact = (act[0] || act[1]) && inrange;
+    V* __restrict__ col = reinterpret_cast<V*>(a.data + (size_t)qy * nx + (qx0 < nx ? qx0 : 0));
+
+    TC F[2][L], Rr[2][L];
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int k = s0 + t;
+        V v;
+        v.x = (TS)0;
+        v.y = (TS)0;
+        if (anyact && k < nz) v = col[(size_t)k * stride2];
+        F[0][t] = (TC)v.x;
+        F[1][t] = (TC)v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        F[0][t] *= tsi[s0 + t];
+        F[1][t] *= tsi[s0 + t];
+    }
+    // downward sweep of both lines (interleaved), first-row back
+    // substitution accumulated as running sums (see k_zsolve)
+    TC cp[2] = {0, 0}, dp[2] = {0, 0}, g[2] = {1, 1}, pi[2] = {1, 1}, ys[2] = {0, 0}, gs[2] = {0, 0};
+#pragma unroll
+    for (int t = 0; t < L - 1; ++t) {
+        const int k = s0 + t;
+        const TC A = ta[k], C = tc[k], B0 = tb[k], M = tm[k];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const TC r = (TC)1 / (B0 + sigma[h] * M - A * cp[h]);
+            Rr[h][t] = r;
+            dp[h] = (F[h][t] - A * dp[h]) * r;
+            g[h] = -A * g[h] * r;
+            ys[h] += dp[h] * pi[h];
+            gs[h] += g[h] * pi[h];
+            cp[h] = C * r;
+            pi[h] *= -cp[h];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    const int me = threadIdx.x;
+    TC al[2], be[2], ga[2], ph[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        sh[0][2 * me + h] = ys[h];    // Y_first
+        sh[1][2 * me + h] = gs[h];    // G_first
+        sh[2][2 * me + h] = pi[h];    // H_first
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        al[h] = 0;
+        be[h] = 1;
+        ga[h] = 0;
+        ph[h] = 0;
+        if (inrange) {
+            const int e = s0 + L - 1;
+            const TC Ae = ta[e], Ce = tc[e], Be = tb[e] + sigma[h] * tm[e];
+            al[h] = Ae * g[h];
+            be[h] = Be - Ae * cp[h];
+            ph[h] = F[h][L - 1] - Ae * dp[h];
+            if (p + 1 < P) {
+                const int nb = 2 * (me + TXL2) + h;
+                be[h] += Ce * sh[1][nb];
+                ga[h] = Ce * sh[2][nb];
+                ph[h] -= Ce * sh[0][nb];
+            }
+        }
+    }
+    // parallel cyclic reduction of the reduced systems of both lines
+    for (int s = 1; s < P; s <<= 1) {
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            sh[0][2 * me + h] = al[h];
+            sh[1][2 * me + h] = be[h];
+            sh[2][2 * me + h] = ga[h];
+            sh[3][2 * me + h] = ph[h];
+        }
+        __syncthreads();
+        if (inrange) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                TC k1 = 0, k2 = 0, alm = 0, gam = 0, phm = 0, alp = 0, gap = 0, php = 0;
+                if (p - s >= 0) {
+                    const int id = 2 * (me - s * TXL2) + h;
+                    k1 = al[h] / sh[1][id];
+                    alm = sh[0][id];
+                    gam = sh[2][id];
+                    phm = sh[3][id];
+                }
+                if (p + s < P) {
+                    const int id = 2 * (me + s * TXL2) + h;
+                    k2 = ga[h] / sh[1][id];
+                    alp = sh[0][id];
+                    gap = sh[2][id];
+                    php = sh[3][id];
+                }
+                be[h] = be[h] - k1 * gam - k2 * alp;
+                ph[h] = ph[h] - k1 * phm - k2 * php;
+                al[h] = -k1 * alm;
+                ga[h] = -k2 * gap;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) sh[0][2 * me + h] = ph[h] / be[h];
+    __syncthreads();
+    TC XR[2], XL[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        XR[h] = sh[0][2 * me + h];
+        XL[h] = (p > 0) ? sh[0][2 * (me - TXL2) + h] : (TC)0;
+    }
+    TC prev[2] = {XL[0], XL[1]};
+#pragma unroll
+    for (int t = 0; t < L - 1; ++t) {
+        const TC A = ta[s0 + t];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            prev[h] = (F[h][t] - A * prev[h]) * Rr[h][t];
+            F[h][t] = prev[h];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    TC nxt[2] = {XR[0], XR[1]};
+    F[0][L - 1] = XR[0];
+    F[1][L - 1] = XR[1];
+#pragma unroll
+    for (int t = L - 2; t >= 0; --t) {
+        const TC C = tc[s0 + t];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            nxt[h] = F[h][t] - C * Rr[h][t] * nxt[h];
+            F[h][t] = nxt[h];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (anyact) {
+        V* out = col + (size_t)s0 * stride2;
+        asm volatile("" : "+v"(out));
+        TS* outs = reinterpret_cast<TS*>(out);
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            if (s0 + t < nz) {
+                const TC so = tso[s0 + t];
+                if (act[0] && act[1]) {
+                    V v;
+                    v.x = (TS)(F[0][t] * so);
+                    v.y = (TS)(F[1][t] * so);
+                    out[(size_t)t * stride2] = v;
+                } else if (act[0]) {
+                    outs[(size_t)t * 2 * stride2] = (TS)(F[0][t] * so);
+                } else {
+                    outs[(size_t)t * 2 * stride2 + 1] = (TS)(F[1][t] * so);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // (0,0) mode: singular z line (zero-flux walls).  Removes the dz-weighted
 // mean of the scaled right-hand side (compatibility), integrates the flux
 // F_k = sum_{k'<k} dz_k' f_k', sums p_k = sum_{k'<=k} h_k' F_k', and pins
@@ -362,12 +572,25 @@ struct GradArgs {
 
 template <typename TIO, typename TP>
 __global__ __launch_bounds__(256) void k_grad(GradArgs<TIO, TP> a) {
-    // one x-row (k, j) per workgroup, rows in XCD-contiguous order so the
-    // j-1 and k-1 neighbour rows of p are mostly L2 hits
-    const long row = xcd_remap(blockIdx.x, gridDim.x);
+    // one x-row (k, j) per workgroup in XCD-contiguous order.  When ny is a
+    // multiple of GJ the rows go in tiles of GJ rows, plane by plane inside a
+    // tile: the k-1 row of p was read GJ workgroups earlier and the j-1 row
+    // one workgroup earlier on the same XCD (L2 hits), except at tile edges
+    constexpr int GJ = 8;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
     const int nx = a.nx, ny = a.ny;
-    const int k = (int)(row / ny);
-    const int j = (int)(row - (long)k * ny);
+    int k, j;
+    if (ny % GJ == 0) {
+        const int per = a.nz * GJ;
+        const int jt = b / per;
+        const int rem = b - jt * per;
+        k = rem / GJ;
+        j = jt * GJ + (rem - k * GJ);
+    } else {
+        k = b / ny;
+        j = b - k * ny;
+    }
+    const long row = (long)k * ny + j;
     const size_t base = (size_t)row * nx;
     TIO* __restrict__ u = a.u;
     TIO* __restrict__ v = a.v;
@@ -389,18 +612,34 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs<TIO, TP> a) {
     }
 }
 
-// deterministic sum of the per-block partials (one workgroup)
-__global__ __launch_bounds__(256) void k_sum_partials(const double* part, int nblk, double* out) {
-    __shared__ double sh[2 * 4];
-    double a = 0.0, b = 0.0;
-    for (int t = threadIdx.x; t < nblk; t += 256) {
-        a += part[2 * t];
-        b += part[2 * t + 1];
+// deterministic sum of the per-block partial triples (one workgroup of 1024
+// threads, 8 blocks' triples in flight per thread, fixed summation order);
+// optionally also mean_out = (third sum) * mean_scale
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* part, int nblk, double* out, double* mean_out,
+                                                      double mean_scale) {
+    __shared__ double sh[3 * 16];
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int t0 = threadIdx.x; t0 < nblk; t0 += 8 * 1024) {
+        double v[8][3];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int t = t0 + r * 1024;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[r][q] = (t < nblk) ? part[3 * t + q] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            a += v[r][0];
+            b += v[r][1];
+            c += v[r][2];
+        }
     }
-    block_sum2<256>(a, b, sh);
+    block_sum3<1024>(a, b, c, sh);
     if (threadIdx.x == 0) {
         out[0] = a;
         out[1] = b;
+        out[2] = c;
+        if (mean_out) *mean_out = c * mean_scale;
     }
 }
 

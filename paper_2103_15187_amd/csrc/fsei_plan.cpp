@@ -67,7 +67,7 @@ void compute_layout(fsei_plan_impl* p) {
     p->ws_scalars = off;
     off = round_up(off + fsei_plan_impl::kScalars * sizeof(double), kAlign);
     p->ws_partials = off;
-    off = round_up(off + 2 * p->n_partials * sizeof(double), kAlign);
+    off = round_up(off + 3 * p->n_partials * sizeof(double), kAlign);
     p->ws_list = off;
     p->ws_list_bytes = (size_t)p->nlist * sizeof(int);
     off = round_up(off + p->ws_list_bytes, kAlign);

@@ -95,7 +95,7 @@ struct fsei_plan_impl {
     size_t ws_field3 = 0, ws_field3_bytes = 0;     // refine: FP64 pressure when the caller passes none
     size_t ws_list = 0, ws_list_bytes = 0;         // mode lines solved in FP64 by FP32 plans
     size_t ws_total = 0;
-    size_t n_partials = 0;                          // per-block partial sums (pairs)
+    size_t n_partials = 0;                          // per-block partial sums (triples)
     static constexpr int kScalars = 64;
 
     // FP32 plans: lines with |lambda_x + lambda_y| < sigma_thr (condition

@@ -41,27 +41,31 @@ __device__ __forceinline__ long xcd_remap(long i, long n) {
     return x * q + (x < r ? x : r) + t;
 }
 
-// deterministic block sum of two values (result valid in thread 0)
+// deterministic block sum of three values (result valid in thread 0)
 template <int NTHR>
-__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+__device__ __forceinline__ void block_sum3(double& a, double& b, double& c, double* sh) {
     for (int off = 32; off > 0; off >>= 1) {
         a += __shfl_down(a, off, 64);
         b += __shfl_down(b, off, 64);
+        c += __shfl_down(c, off, 64);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) {
-        sh[2 * wid] = a;
-        sh[2 * wid + 1] = b;
+        sh[3 * wid] = a;
+        sh[3 * wid + 1] = b;
+        sh[3 * wid + 2] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double sa = 0.0, sb = 0.0;
+        double sa = 0.0, sb = 0.0, sc = 0.0;
         for (int w = 0; w < NTHR / 64; ++w) {
-            sa += sh[2 * w];
-            sb += sh[2 * w + 1];
+            sa += sh[3 * w];
+            sb += sh[3 * w + 1];
+            sc += sh[3 * w + 2];
         }
         a = sa;
         b = sb;
+        c = sc;
     }
     __syncthreads();
 }
@@ -152,6 +156,89 @@ __device__ __forceinline__ void row_kj(int k0, int j0, int l, int ny, int& k, in
 }
 
 // ---------------------------------------------------------------------------
+// Fixed-length full-tile paths.  The variants with NF > 0 are launched only
+// when every tile is full (the host checks), so each thread's rows, columns
+// and LDS slots are compile-time functions of its lane: loads and stores
+// address a workgroup-uniform row pointer (scalar registers) plus the lane's
+// 32-bit column, and every boundary test is either per row (uniform) or per
+// lane and fixed for the whole launch.  No bounds test remains in the loops.
+// ---------------------------------------------------------------------------
+
+// neighbour rows of x-row (k, j): element offsets from the row and whether
+// the neighbour takes part (a wall has no neighbour beyond it; an absent
+// neighbour's offset is 0 so its load stays in bounds and is discarded)
+struct RowNb {
+    long yp, ym, zp, zm;
+    bool hyp, hym, hzp, hzm;
+};
+__device__ __forceinline__ RowNb row_nb(int k, int j, int N, int ny, int nz, int bcy) {
+    const bool per = bcy == FSEI_BC_PERIODIC;
+    const long plane = (long)N * ny;
+    RowNb r;
+    r.hyp = (j + 1 < ny) || per;
+    r.yp = (j + 1 < ny) ? (long)N : (per ? -(long)(ny - 1) * N : 0L);
+    r.hym = (j >= 1) || per;
+    r.ym = (j >= 1) ? -(long)N : (per ? (long)(ny - 1) * N : 0L);
+    r.hzp = k + 1 < nz;
+    r.zp = r.hzp ? plane : 0L;
+    r.hzm = k >= 1;
+    r.zm = r.hzm ? -plane : 0L;
+    return r;
+}
+
+// x neighbours of column i: wrapped indices (always in [0, N)) and whether
+// they take part
+struct ColNb {
+    unsigned i, ip, im;
+    bool hip, him;
+};
+__device__ __forceinline__ ColNb col_nb(int i, int N, int bcx) {
+    const bool per = bcx == FSEI_BC_PERIODIC;
+    ColNb c;
+    c.i = (unsigned)i;
+    c.ip = (i + 1 < N) ? (unsigned)(i + 1) : 0u;
+    c.im = (i >= 1) ? (unsigned)(i - 1) : (unsigned)(N - 1);
+    c.hip = (i + 1 < N) || per;
+    c.him = (i >= 1) || per;
+    return c;
+}
+
+// forward post-processing from the four values at rows m and mm = (N - m) % N
+// of one pair (selects instead of branches; same arithmetic as post_fwd)
+template <typename T>
+__device__ __forceinline__ void post_fwd_v(int bc, bool lo, T zr, T zi, T cr, T ci, T wr, T wi, T& xa, T& xb) {
+    const T half = (T)0.5;
+    if (bc == FSEI_BC_WALL) {
+        const T ar = (zr + cr) * half, ai = (zi - ci) * half;
+        const T br = (zi + ci) * half, bi = (cr - zr) * half;
+        xa = wr * ar - wi * ai;
+        xb = wr * br - wi * bi;
+    } else {
+        xa = lo ? (zr + cr) * half : (ci - zi) * half;
+        xb = lo ? (zi + ci) * half : (zr - cr) * half;
+    }
+}
+
+// whether the fixed y tile of EMAX elements and NTHR threads at length NF
+// gives every thread whole column pairs on an even number of rows per pass
+__host__ __device__ constexpr bool y_fixed_ok(int emax, int nthr, int nf) {
+    return tile_nseq(emax, nf) > 0 && nthr % tile_nseq(emax, nf) == 0 && nf % (nthr / tile_nseq(emax, nf)) == 0 &&
+           (nthr / tile_nseq(emax, nf)) % 2 == 0;
+}
+
+// two adjacent values of a field as one vector access
+template <typename T>
+struct Vec2T;
+template <>
+struct Vec2T<double> {
+    using type = double2;
+};
+template <>
+struct Vec2T<float> {
+    using type = float2;
+};
+
+// ---------------------------------------------------------------------------
 // x forward: prologue (divergence / transposed gradient / residual / copy)
 // fused with the forward x transform
 // ---------------------------------------------------------------------------
@@ -178,7 +265,8 @@ struct XFwdArgs {
     // outputs
     TO* out;
     double* out_f;      // optional FP64 copy of the prologue value
-    double* partials;   // optional per-block (sum v^2, sum v)
+    double* partials;   // optional per-block (sum v^2, sum v, sum dzw_k v)
+    const double* dzw;  // with partials: z weights of the third sum (dz_k), or null
     const TO* twc;
     const TO* tws;
     const TO* dctc;
@@ -231,81 +319,208 @@ __device__ __forceinline__ TI x_prologue(const XFwdArgs<TI, TO>& a, size_t base,
     }
 }
 
+// The same stencil values on the fixed-length path: `ro` is the offset of the
+// row's first cell (uniform), `rn` its neighbour rows, `cn` the lane's column.
+// Every load is in bounds; absent neighbours are replaced by zero afterwards,
+// so the arithmetic is that of x_prologue.
+template <typename TI, typename TO, int PRO>
+__device__ __forceinline__ TI x_prologue_row(const XFwdArgs<TI, TO>& a, size_t ro, int k, const RowNb& rn,
+                                             const ColNb& cn) {
+    if constexpr (PRO == PRO_COPY) {
+        return (TI)a.f[ro + cn.i];
+    } else if constexpr (PRO == PRO_RESID) {
+        const double* __restrict__ p = a.p + ro;
+        const double pc = p[cn.i];
+        const double pxp = p[cn.ip], pxm = p[cn.im];
+        const double pyp = (p + rn.yp)[cn.i], pym = (p + rn.ym)[cn.i];
+        const double pzp = (p + rn.zp)[cn.i], pzm = (p + rn.zm)[cn.i];
+        const double fc = a.f[ro + cn.i];
+        const double lx = (cn.hip ? pxp - pc : 0.0) + (cn.him ? pxm - pc : 0.0);
+        const double ly = (rn.hyp ? pyp - pc : 0.0) + (rn.hym ? pym - pc : 0.0);
+        const double lz = (rn.hzp ? a.zc[k] * (pzp - pc) : 0.0) + (rn.hzm ? a.za[k] * (pzm - pc) : 0.0);
+        const double lap = lx * a.idx2 + ly * a.idy2 + lz;
+        return (TI)((fc - a.scal[0]) - lap);
+    } else {
+        const TI zero = (TI)0;
+        const TI* __restrict__ u = a.u + ro;
+        const TI* __restrict__ v = a.v + ro;
+        const TI* __restrict__ w = a.w + ro;
+        const TI uc = u[cn.i], uh = u[cn.ip];
+        const TI vc = v[cn.i], vh = (v + rn.yp)[cn.i];
+        const TI wc = w[cn.i], wh = (w + rn.zp)[cn.i];
+        TI val = ((cn.hip ? uh : zero) - (cn.him ? uc : zero)) * a.idx +
+                 ((rn.hyp ? vh : zero) - (rn.hym ? vc : zero)) * a.idy +
+                 (a.zeta[k] * (rn.hzp ? wh : zero) - a.eta[k] * (rn.hzm ? wc : zero));
+        val *= a.alpha;
+        if constexpr (PRO == PRO_DIV_ADJ) {
+            if (a.gp) val += a.beta * a.gp[ro + cn.i];
+        }
+        return val;
+    }
+}
+
 template <typename TI, typename TO, int PRO, int EMAX, int NTHR, int NF>
 __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
     __shared__ TO sre[lds_elems(EMAX)];
     __shared__ TO sim[lds_elems(EMAX)];
-    __shared__ double sred[2 * (NTHR / 64)];
+    __shared__ double sred[3 * (NTHR / 64)];
+    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF) : 0;   // pairs per tile, fixed path
     const int N = NF > 0 ? NF : a.nx;
     const int SP = seq_stride(N);
-    const int nl = 2 * a.nseq;
-    const int total = nl * N;
-    const long row0 = xcd_remap(blockIdx.x, gridDim.x) * nl;
+    const int nseq = NF > 0 ? NSF : a.nseq;
+    const int nl = 2 * nseq;
     const long nrows = (long)a.ny * a.nz;
-    const int k0 = (int)(row0 / a.ny);
-    const int j0 = (int)(row0 - (long)k0 * a.ny);
+    long row0;
+    int k0, j0;
+    if constexpr (NF > 0) {
+        // tiles in (row tile, plane) order, plane fastest: the tile of the
+        // same rows one plane up, whose rows of w (or p) this tile also
+        // reads, is the next workgroup on the same XCD (an L2 hit)
+        const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+        const int jt = b / a.nz;
+        k0 = b - jt * a.nz;
+        j0 = jt * nl;
+        row0 = (long)k0 * a.ny + j0;
+    } else {
+        row0 = xcd_remap(blockIdx.x, gridDim.x) * nl;
+        k0 = (int)(row0 / a.ny);
+        j0 = (int)(row0 - (long)k0 * a.ny);
+    }
     const size_t base = (size_t)row0 * N;
     TO* twl = lds_twiddles<TO, NTHR>(a.twc, a.tws, N);
     double* __restrict__ out_f = a.out_f;
-    double ss = 0.0, s1 = 0.0;
-    constexpr int PER = 2 * EMAX / NTHR;   // elements per thread, >= total / NTHR
-    constexpr int BAT = (PER % 4 == 0) ? 4 : 1;
-    for (int r0 = 0; r0 < PER; r0 += BAT) {
-        TI val[BAT];
+    double ss = 0.0, s1 = 0.0, s2 = 0.0;
+    if constexpr (NF > 0) {
+        static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
+        constexpr int CPR = NF / NTHR, NL = 2 * NSF;
+        constexpr int RB = (NL % 4 == 0) ? 4 : ((NL % 2 == 0) ? 2 : 1);   // rows per load batch
+        ColNb cn[CPR];
+        int lp[CPR];
 #pragma unroll
-        for (int r = 0; r < BAT; ++r) {
-            const int e = threadIdx.x + (r0 + r) * NTHR;
-            val[r] = (TI)0;
-            if (e < total) {
-                const int l = e / N;
-                const int i = e - l * N;
-                if (row0 + l < nrows) {
-                    int k, j;
-                    row_kj(k0, j0, l, a.ny, k, j);
-                    val[r] = x_prologue<TI, TO, PRO>(a, base, k, j, i, e, N);
+        for (int c = 0; c < CPR; ++c) {
+            const int i = threadIdx.x + c * NTHR;
+            cn[c] = col_nb(i, NF, a.bcx);
+            lp[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
+        }
+#pragma unroll
+        for (int l0 = 0; l0 < NL; l0 += RB) {
+            TI val[RB][CPR];
+#pragma unroll
+            for (int lr = 0; lr < RB; ++lr) {
+                // the host launches this path only when ny is a multiple of
+                // the rows per tile, so all rows of a tile share plane k0
+                const int l = l0 + lr;
+                const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+#pragma unroll
+                for (int c = 0; c < CPR; ++c)
+                    val[lr][c] = x_prologue_row<TI, TO, PRO>(a, base + (size_t)l * NF, k0, rn, cn[c]);
+            }
+#pragma unroll
+            for (int lr = 0; lr < RB; ++lr) {
+                const int l = l0 + lr;
+#pragma unroll
+                for (int c = 0; c < CPR; ++c) {
+                    const double v = (double)val[lr][c];
+                    if (out_f) out_f[base + (size_t)l * NF + cn[c].i] = v;
+                    ss += v * v;
+                    s1 += v;
+                    TO* dst = (l & 1) ? sim : sre;
+                    dst[(l >> 1) * SP + lp[c]] = (TO)val[lr][c];
                 }
             }
         }
+        if (a.dzw) s2 = a.dzw[k0] * s1;   // every row of the tile is in plane k0
+    } else {
+        const int total = nl * N;
+        constexpr int PER = 2 * EMAX / NTHR;   // elements per thread, >= total / NTHR
+        constexpr int BAT = (PER % 4 == 0) ? 4 : 1;
+        for (int r0 = 0; r0 < PER; r0 += BAT) {
+            TI val[BAT];
 #pragma unroll
-        for (int r = 0; r < BAT; ++r) {
-            const int e = threadIdx.x + (r0 + r) * NTHR;
-            if (e < total) {
-                const int l = e / N;
-                const int i = e - l * N;
-                if (row0 + l < nrows) {
-                    if (out_f) out_f[base + e] = (double)val[r];
-                    ss += (double)val[r] * (double)val[r];
-                    s1 += (double)val[r];
+            for (int r = 0; r < BAT; ++r) {
+                const int e = threadIdx.x + (r0 + r) * NTHR;
+                val[r] = (TI)0;
+                if (e < total) {
+                    const int l = e / N;
+                    const int i = e - l * N;
+                    if (row0 + l < nrows) {
+                        int k, j;
+                        row_kj(k0, j0, l, a.ny, k, j);
+                        val[r] = x_prologue<TI, TO, PRO>(a, base, k, j, i, e, N);
+                    }
                 }
-                const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
-                if (l & 1) sim[li(l >> 1, n, SP)] = (TO)val[r];
-                else sre[li(l >> 1, n, SP)] = (TO)val[r];
+            }
+#pragma unroll
+            for (int r = 0; r < BAT; ++r) {
+                const int e = threadIdx.x + (r0 + r) * NTHR;
+                if (e < total) {
+                    const int l = e / N;
+                    const int i = e - l * N;
+                    if (row0 + l < nrows) {
+                        if (out_f) out_f[base + e] = (double)val[r];
+                        ss += (double)val[r] * (double)val[r];
+                        s1 += (double)val[r];
+                        if (a.dzw) {
+                            int k, j;
+                            row_kj(k0, j0, l, a.ny, k, j);
+                            s2 += a.dzw[k] * (double)val[r];
+                        }
+                    }
+                    const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
+                    if (l & 1) sim[li(l >> 1, n, SP)] = (TO)val[r];
+                    else sre[li(l >> 1, n, SP)] = (TO)val[r];
+                }
             }
         }
     }
     if (a.partials) {
-        block_sum2<NTHR>(ss, s1, sred);
+        block_sum3<NTHR>(ss, s1, s2, sred);
         if (threadIdx.x == 0) {
-            a.partials[2 * blockIdx.x] = ss;
-            a.partials[2 * blockIdx.x + 1] = s1;
+            a.partials[3 * blockIdx.x] = ss;
+            a.partials[3 * blockIdx.x + 1] = s1;
+            a.partials[3 * blockIdx.x + 2] = s2;
         }
     } else {
         __syncthreads();
     }
     if (a.out == nullptr) return;   // norm-only pass (uniform over the block)
-    fft_lds<TO, EMAX, NTHR, -1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
+    fft_lds<TO, EMAX, NTHR, -1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
     TO* __restrict__ out = a.out + base;
-    constexpr int PST = EMAX / NTHR;
+    if constexpr (NF > 0) {
+        constexpr int CPR = NF / NTHR;
 #pragma unroll
-    for (int r = 0; r < PST; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < a.nseq * N) {
-            const int s = e / N;
-            const int m = e - s * N;
-            TO xa, xb;
-            post_fwd<TO>(sre, sim, s, SP, N, m, a.bcx, a.dctc, a.dcts, xa, xb);
-            if (row0 + 2 * s < nrows) out[2 * s * N + m] = xa;
-            if (row0 + 2 * s + 1 < nrows) out[(2 * s + 1) * N + m] = xb;
+        for (int c = 0; c < CPR; ++c) {
+            const int m = threadIdx.x + c * NTHR;
+            const int mm = (m == 0) ? 0 : NF - m;
+            const int lm = li(0, m, SP), lmm = li(0, mm, SP);
+            const bool lo = 2 * m <= NF;
+            TO wr = (TO)1, wi = (TO)0;
+            if (a.bcx == FSEI_BC_WALL) {
+                wr = a.dctc[m];
+                wi = -a.dcts[m];
+            }
+#pragma unroll
+            for (int s = 0; s < NSF; ++s) {
+                TO xa, xb;
+                post_fwd_v<TO>(a.bcx, lo, sre[s * SP + lm], sim[s * SP + lm], sre[s * SP + lmm], sim[s * SP + lmm],
+                               wr, wi, xa, xb);
+                out[(2 * s) * NF + m] = xa;
+                out[(2 * s + 1) * NF + m] = xb;
+            }
+        }
+    } else {
+        constexpr int PST = EMAX / NTHR;
+#pragma unroll
+        for (int r = 0; r < PST; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < nseq * N) {
+                const int s = e / N;
+                const int m = e - s * N;
+                TO xa, xb;
+                post_fwd<TO>(sre, sim, s, SP, N, m, a.bcx, a.dctc, a.dcts, xa, xb);
+                if (row0 + 2 * s < nrows) out[2 * s * N + m] = xa;
+                if (row0 + 2 * s + 1 < nrows) out[(2 * s + 1) * N + m] = xb;
+            }
         }
     }
 }
@@ -332,52 +547,112 @@ template <typename T, typename TP, int EPI, int EMAX, int NTHR, int NF>
 __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
     __shared__ T sre[lds_elems(EMAX)];
     __shared__ T sim[lds_elems(EMAX)];
+    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF) : 0;
     const int N = NF > 0 ? NF : a.nx;
     const int SP = seq_stride(N);
-    const int nl = 2 * a.nseq;
+    const int nseq = NF > 0 ? NSF : a.nseq;
+    const int nl = 2 * nseq;
     const long row0 = xcd_remap(blockIdx.x, gridDim.x) * nl;
     const long nrows = (long)a.ny * a.nz;
     const size_t base = (size_t)row0 * N;
     const T* __restrict__ in = a.in + base;
     T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
-    constexpr int PLD = EMAX / NTHR;
+    if constexpr (NF > 0) {
+        static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
+        constexpr int CPR = NF / NTHR;
 #pragma unroll
-    for (int r = 0; r < PLD; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < a.nseq * N) {
-            const int s = e / N;
-            const int m = e - s * N;
-            const int nm = (m == 0) ? 0 : N - m;
-            T xam = 0, xanm = 0, xbm = 0, xbnm = 0;
-            if (row0 + 2 * s < nrows) {
-                xam = in[2 * s * N + m];
-                xanm = in[2 * s * N + nm];
+        for (int c = 0; c < CPR; ++c) {
+            const int m = threadIdx.x + c * NTHR;
+            const int nm = (m == 0) ? 0 : NF - m;
+            const int lm = li(0, m, SP);
+            T xam[NSF], xanm[NSF], xbm[NSF], xbnm[NSF];
+#pragma unroll
+            for (int s = 0; s < NSF; ++s) {
+                xam[s] = in[(2 * s) * NF + m];
+                xanm[s] = in[(2 * s) * NF + nm];
+                xbm[s] = in[(2 * s + 1) * NF + m];
+                xbnm[s] = in[(2 * s + 1) * NF + nm];
             }
-            if (row0 + 2 * s + 1 < nrows) {
-                xbm = in[(2 * s + 1) * N + m];
-                xbnm = in[(2 * s + 1) * N + nm];
+#pragma unroll
+            for (int s = 0; s < NSF; ++s) {
+                T zr, zi;
+                pre_inv<T>(NF, m, a.bcx, xam[s], xanm[s], xbm[s], xbnm[s], a.dctc, a.dcts, zr, zi);
+                sre[s * SP + lm] = zr;
+                sim[s * SP + lm] = zi;
             }
-            T zr, zi;
-            pre_inv<T>(N, m, a.bcx, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
-            sre[li(s, m, SP)] = zr;
-            sim[li(s, m, SP)] = zi;
+        }
+    } else {
+        constexpr int PLD = EMAX / NTHR;
+#pragma unroll
+        for (int r = 0; r < PLD; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < nseq * N) {
+                const int s = e / N;
+                const int m = e - s * N;
+                const int nm = (m == 0) ? 0 : N - m;
+                T xam = 0, xanm = 0, xbm = 0, xbnm = 0;
+                if (row0 + 2 * s < nrows) {
+                    xam = in[2 * s * N + m];
+                    xanm = in[2 * s * N + nm];
+                }
+                if (row0 + 2 * s + 1 < nrows) {
+                    xbm = in[(2 * s + 1) * N + m];
+                    xbnm = in[(2 * s + 1) * N + nm];
+                }
+                T zr, zi;
+                pre_inv<T>(N, m, a.bcx, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
+                sre[li(s, m, SP)] = zr;
+                sim[li(s, m, SP)] = zi;
+            }
         }
     }
     __syncthreads();
-    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
+    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
     TP* __restrict__ out = a.out + base;
-    constexpr int PST = 2 * EMAX / NTHR;
+    if constexpr (NF > 0) {
+        constexpr int CPR = NF / NTHR, NL = 2 * NSF;
+        int ln[CPR];
 #pragma unroll
-    for (int r = 0; r < PST; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < nl * N) {
-            const int l = e / N;
-            const int i = e - l * N;
-            if (row0 + l < nrows) {
-                const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
-                const T val = (l & 1) ? sim[li(l >> 1, n, SP)] : sre[li(l >> 1, n, SP)];
-                if constexpr (EPI == EPI_ACC) out[e] += (TP)val;
-                else out[e] = (TP)val;
+        for (int c = 0; c < CPR; ++c) {
+            const int i = threadIdx.x + c * NTHR;
+            ln[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
+        }
+        if constexpr (EPI == EPI_ACC) {
+            TP old[NL][CPR];
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+#pragma unroll
+                for (int c = 0; c < CPR; ++c) old[l][c] = out[l * NF + threadIdx.x + c * NTHR];
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+#pragma unroll
+                for (int c = 0; c < CPR; ++c) {
+                    const T val = (l & 1) ? sim[(l >> 1) * SP + ln[c]] : sre[(l >> 1) * SP + ln[c]];
+                    out[l * NF + threadIdx.x + c * NTHR] = old[l][c] + (TP)val;
+                }
+        } else {
+#pragma unroll
+            for (int l = 0; l < NL; ++l)
+#pragma unroll
+                for (int c = 0; c < CPR; ++c) {
+                    const T val = (l & 1) ? sim[(l >> 1) * SP + ln[c]] : sre[(l >> 1) * SP + ln[c]];
+                    out[l * NF + threadIdx.x + c * NTHR] = (TP)val;
+                }
+        }
+    } else {
+        constexpr int PST = 2 * EMAX / NTHR;
+#pragma unroll
+        for (int r = 0; r < PST; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < nl * N) {
+                const int l = e / N;
+                const int i = e - l * N;
+                if (row0 + l < nrows) {
+                    const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
+                    const T val = (l & 1) ? sim[li(l >> 1, n, SP)] : sre[li(l >> 1, n, SP)];
+                    if constexpr (EPI == EPI_ACC) out[e] += (TP)val;
+                    else out[e] = (TP)val;
+                }
             }
         }
     }
@@ -402,48 +677,90 @@ template <typename T, int EMAX, int NTHR, int NF>
 __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
     __shared__ T sre[lds_elems(EMAX)];
     __shared__ T sim[lds_elems(EMAX)];
+    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF) : 0;
     const int N = NF > 0 ? NF : a.ny;
     const int SP = seq_stride(N);
     const int nx = a.nx;
-    const int TX = 2 * a.nseq;
+    const int nseq = NF > 0 ? NSF : a.nseq;
+    const int TX = 2 * nseq;
     const int k = blockIdx.x / a.ntile;
     const int tile = blockIdx.x - k * a.ntile;
     const int i0 = tile * TX;
     T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
     T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
-    constexpr int PLD = 2 * EMAX / NTHR;
-    T val[PLD];
+    if constexpr (NF > 0) {
+        // lane: column pair s (= sequence s), rows jr + r * RPP
+        using V2 = typename Vec2T<T>::type;
+        constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
+        static_assert(NTHR % NSF == 0 && NF % RPP == 0 && RPP % 2 == 0, "fixed y tile");
+        const int s = threadIdx.x % NSF, jr = threadIdx.x / NSF;
+        const unsigned lo = (unsigned)(jr * nx + 2 * s);
+        V2 val[NPASS];
 #pragma unroll
-    for (int r = 0; r < PLD; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        const int j = e / TX;
-        const int c = e - j * TX;
-        val[r] = (e < TX * N && i0 + c < nx) ? d[j * nx + c] : (T)0;
-    }
+        for (int r = 0; r < NPASS; ++r) val[r] = *reinterpret_cast<const V2*>(d + (size_t)(r * RPP) * nx + lo);
 #pragma unroll
-    for (int r = 0; r < PLD; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < TX * N) {
+        for (int r = 0; r < NPASS; ++r) {
+            const int j = jr + r * RPP;
+            const int o = s * SP + li(0, (a.bcy == FSEI_BC_WALL) ? mk_pos(j, NF) : j, SP);
+            sre[o] = val[r].x;
+            sim[o] = val[r].y;
+        }
+    } else {
+        constexpr int PLD = 2 * EMAX / NTHR;
+        T val[PLD];
+#pragma unroll
+        for (int r = 0; r < PLD; ++r) {
+            const int e = threadIdx.x + r * NTHR;
             const int j = e / TX;
             const int c = e - j * TX;
-            const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
-            if (c & 1) sim[li(c >> 1, n, SP)] = val[r];
-            else sre[li(c >> 1, n, SP)] = val[r];
+            val[r] = (e < TX * N && i0 + c < nx) ? d[j * nx + c] : (T)0;
+        }
+#pragma unroll
+        for (int r = 0; r < PLD; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < TX * N) {
+                const int j = e / TX;
+                const int c = e - j * TX;
+                const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
+                if (c & 1) sim[li(c >> 1, n, SP)] = val[r];
+                else sre[li(c >> 1, n, SP)] = val[r];
+            }
         }
     }
     __syncthreads();
-    fft_lds<T, EMAX, NTHR, -1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
-    constexpr int PST = EMAX / NTHR;
+    fft_lds<T, EMAX, NTHR, -1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
+    if constexpr (NF > 0) {
+        using V2 = typename Vec2T<T>::type;
+        constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
+        const int s = threadIdx.x % NSF, mr = threadIdx.x / NSF;
+        const unsigned lo = (unsigned)(mr * nx + 2 * s);
 #pragma unroll
-    for (int r = 0; r < PST; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < a.nseq * N) {
-            const int m = e / a.nseq;
-            const int s = e - m * a.nseq;
-            T xa, xb;
-            post_fwd<T>(sre, sim, s, SP, N, m, a.bcy, a.dctc, a.dcts, xa, xb);
-            if (i0 + 2 * s < nx) d[m * nx + 2 * s] = xa;
-            if (i0 + 2 * s + 1 < nx) d[m * nx + 2 * s + 1] = xb;
+        for (int r = 0; r < NPASS; ++r) {
+            const int m = mr + r * RPP;
+            const int mm = (m == 0) ? 0 : NF - m;
+            const int om = s * SP + li(0, m, SP), omm = s * SP + li(0, mm, SP);
+            T wr = (T)1, wi = (T)0;
+            if (a.bcy == FSEI_BC_WALL) {
+                wr = a.dctc[m];
+                wi = -a.dcts[m];
+            }
+            V2 res;
+            post_fwd_v<T>(a.bcy, 2 * m <= NF, sre[om], sim[om], sre[omm], sim[omm], wr, wi, res.x, res.y);
+            *reinterpret_cast<V2*>(d + (size_t)(r * RPP) * nx + lo) = res;
+        }
+    } else {
+        constexpr int PST = EMAX / NTHR;
+#pragma unroll
+        for (int r = 0; r < PST; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < nseq * N) {
+                const int m = e / nseq;
+                const int s = e - m * nseq;
+                T xa, xb;
+                post_fwd<T>(sre, sim, s, SP, N, m, a.bcy, a.dctc, a.dcts, xa, xb);
+                if (i0 + 2 * s < nx) d[m * nx + 2 * s] = xa;
+                if (i0 + 2 * s + 1 < nx) d[m * nx + 2 * s + 1] = xb;
+            }
         }
     }
 }
@@ -452,50 +769,93 @@ template <typename T, int EMAX, int NTHR, int NF>
 __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
     __shared__ T sre[lds_elems(EMAX)];
     __shared__ T sim[lds_elems(EMAX)];
+    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF) : 0;
     const int N = NF > 0 ? NF : a.ny;
     const int SP = seq_stride(N);
     const int nx = a.nx;
-    const int TX = 2 * a.nseq;
+    const int nseq = NF > 0 ? NSF : a.nseq;
+    const int TX = 2 * nseq;
     const int k = blockIdx.x / a.ntile;
     const int tile = blockIdx.x - k * a.ntile;
     const int i0 = tile * TX;
     T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
     T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
-    constexpr int PLD = EMAX / NTHR;
+    if constexpr (NF > 0) {
+        using V2 = typename Vec2T<T>::type;
+        constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
+        static_assert(NTHR % NSF == 0 && NF % RPP == 0 && RPP % 2 == 0, "fixed y tile");
+        const int s = threadIdx.x % NSF, mr = threadIdx.x / NSF;
+        const unsigned lo = (unsigned)(2 * s);
+        V2 A[NPASS], B[NPASS];
 #pragma unroll
-    for (int r = 0; r < PLD; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < a.nseq * N) {
-            const int m = e / a.nseq;
-            const int s = e - m * a.nseq;
-            const int nm = (m == 0) ? 0 : N - m;
-            T xam = 0, xanm = 0, xbm = 0, xbnm = 0;
-            if (i0 + 2 * s < nx) {
-                xam = d[m * nx + 2 * s];
-                xanm = d[nm * nx + 2 * s];
-            }
-            if (i0 + 2 * s + 1 < nx) {
-                xbm = d[m * nx + 2 * s + 1];
-                xbnm = d[nm * nx + 2 * s + 1];
-            }
+        for (int r = 0; r < NPASS; ++r) {
+            const int m = mr + r * RPP;
+            const int nm = (m == 0) ? 0 : NF - m;
+            A[r] = *reinterpret_cast<const V2*>(d + (size_t)m * nx + lo);
+            B[r] = *reinterpret_cast<const V2*>(d + (size_t)nm * nx + lo);
+        }
+#pragma unroll
+        for (int r = 0; r < NPASS; ++r) {
+            const int m = mr + r * RPP;
             T zr, zi;
-            pre_inv<T>(N, m, a.bcy, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
-            sre[li(s, m, SP)] = zr;
-            sim[li(s, m, SP)] = zi;
+            pre_inv<T>(NF, m, a.bcy, A[r].x, B[r].x, A[r].y, B[r].y, a.dctc, a.dcts, zr, zi);
+            const int o = s * SP + li(0, m, SP);
+            sre[o] = zr;
+            sim[o] = zi;
+        }
+    } else {
+        constexpr int PLD = EMAX / NTHR;
+#pragma unroll
+        for (int r = 0; r < PLD; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < nseq * N) {
+                const int m = e / nseq;
+                const int s = e - m * nseq;
+                const int nm = (m == 0) ? 0 : N - m;
+                T xam = 0, xanm = 0, xbm = 0, xbnm = 0;
+                if (i0 + 2 * s < nx) {
+                    xam = d[m * nx + 2 * s];
+                    xanm = d[nm * nx + 2 * s];
+                }
+                if (i0 + 2 * s + 1 < nx) {
+                    xbm = d[m * nx + 2 * s + 1];
+                    xbnm = d[nm * nx + 2 * s + 1];
+                }
+                T zr, zi;
+                pre_inv<T>(N, m, a.bcy, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
+                sre[li(s, m, SP)] = zr;
+                sim[li(s, m, SP)] = zi;
+            }
         }
     }
     __syncthreads();
-    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, a.nseq, a.fp, twl, twl + N);
-    constexpr int PST = 2 * EMAX / NTHR;
+    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
+    if constexpr (NF > 0) {
+        using V2 = typename Vec2T<T>::type;
+        constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
+        const int s = threadIdx.x % NSF, jr = threadIdx.x / NSF;
+        const unsigned lo = (unsigned)(jr * nx + 2 * s);
 #pragma unroll
-    for (int r = 0; r < PST; ++r) {
-        const int e = threadIdx.x + r * NTHR;
-        if (e < TX * N) {
-            const int j = e / TX;
-            const int c = e - j * TX;
-            if (i0 + c < nx) {
-                const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
-                d[j * nx + c] = (c & 1) ? sim[li(c >> 1, n, SP)] : sre[li(c >> 1, n, SP)];
+        for (int r = 0; r < NPASS; ++r) {
+            const int j = jr + r * RPP;
+            const int o = s * SP + li(0, (a.bcy == FSEI_BC_WALL) ? mk_pos(j, NF) : j, SP);
+            V2 res;
+            res.x = sre[o];
+            res.y = sim[o];
+            *reinterpret_cast<V2*>(d + (size_t)(r * RPP) * nx + lo) = res;
+        }
+    } else {
+        constexpr int PST = 2 * EMAX / NTHR;
+#pragma unroll
+        for (int r = 0; r < PST; ++r) {
+            const int e = threadIdx.x + r * NTHR;
+            if (e < TX * N) {
+                const int j = e / TX;
+                const int c = e - j * TX;
+                if (i0 + c < nx) {
+                    const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
+                    d[j * nx + c] = (c & 1) ? sim[li(c >> 1, n, SP)] : sre[li(c >> 1, n, SP)];
+                }
             }
         }
     }

@@ -219,3 +219,73 @@ def test_refine_fixed_iterations_and_not_converged():
     plan0 = F.Plan.from_spec(spec, precision=F.PREC_FP32_REFINE, rtol=0.0, max_iter=2)
     _, info = plan0.project(dev(u), dev(v), dev(w), info=True)
     assert info["iterations"] == 2 and info["rel_residual"] < 1e-9
+
+
+# ---- fixed-length transform kernels (compile-time length 512) --------------
+# x kernels: nx = 512 with ny a multiple of the 8 rows of a tile; y kernels:
+# ny = 512 with nx a multiple of the tile width (16 FP64 / 32 FP32 columns).
+FIXED = [((512, 16, 6), (WALL, WALL)), ((512, 24, 5), (PERIODIC, PERIODIC)), ((512, 8, 7), (PERIODIC, WALL)),
+         ((32, 512, 5), (WALL, WALL)), ((64, 512, 4), (PERIODIC, PERIODIC)), ((16, 512, 6), (WALL, PERIODIC)),
+         ((512, 512, 2), (WALL, WALL)), ((512, 512, 3), (PERIODIC, WALL))]
+
+
+@pytest.mark.parametrize("dims,bc", FIXED)
+def test_project_fp64_fixed_length(dims, bc):
+    nx, ny, nz = dims
+    spec = W.small_spec(nx, ny, nz, bc[0], bc[1], lx=4.0, ly=3.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, nx + 3 * ny + 7 * nz)
+    ru, rv, rw, rp = oracle.project(u, v, w, g, dt=0.8)
+    gu, gv, gw, gp, _ = run_project(spec, u, v, w, dt=0.8)
+    errs = [rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))]
+    print(f"dims={dims} bc={bc} errs", errs)
+    assert max(errs) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,bc", [((512, 16, 6), (PERIODIC, WALL)), ((32, 512, 4), (WALL, PERIODIC)),
+                                     ((512, 512, 2), (WALL, WALL))])
+def test_backward_fp64_fixed_length(dims, bc):
+    F = fsei()
+    spec = W.small_spec(*dims, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
+    g = grid_of(spec)
+    r = W.rng(23)
+    gu, gv, gw, gp = (r.standard_normal(spec.shape) for _ in range(4))
+    for a, m in zip((gu, gv, gw), W.dead_face_masks(spec)):
+        a[m] = 0
+    ref = oracle.project_adjoint(gu, gv, gw, gp, g, dt=0.6)
+    plan = F.Plan.from_spec(spec)
+    a, b, c = dev(gu), dev(gv), dev(gw)
+    plan.project_backward(a, b, c, dev(gp), dt=0.6)
+    torch.cuda.synchronize()
+    for x, y in zip((host(a), host(b), host(c)), ref):
+        assert rel(x, y) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,bc", [((512, 8, 4), (WALL, WALL)), ((32, 512, 3), (PERIODIC, PERIODIC))])
+def test_poisson_solve_fixed_length(dims, bc):
+    F = fsei()
+    spec = W.small_spec(*dims, bc[0], bc[1], lx=2.0, ly=1.5, lz=3.0, stretch=2.0)
+    g = grid_of(spec)
+    f = W.rng(31).standard_normal(spec.shape)
+    rp = oracle.poisson_solve(f, g)
+    p = F.Plan.from_spec(spec).poisson_solve(dev(f))
+    torch.cuda.synchronize()
+    assert rel(host(p), rp) <= 1e-12
+
+
+@pytest.mark.parametrize("dims,bc", [((512, 32, 12), (WALL, WALL)), ((64, 512, 10), (PERIODIC, WALL)),
+                                     ((512, 512, 4), (PERIODIC, PERIODIC))])
+def test_fp32_and_refine_fixed_length(dims, bc):
+    F = fsei()
+    spec = W.small_spec(*dims, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 77)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    fu, fv, fw, fp, _ = run_project(spec, u, v, w, precision=F.PREC_FP32)
+    e32 = max(rel(a, b) for a, b in ((fu, ru), (fv, rv), (fw, rw)))
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6)
+    print(f"dims={dims} fp32 velocity err {e32:.2e} refine info {info}")
+    assert e32 <= 2e-5
+    assert info["rel_residual"] <= 1e-10
+    assert oracle.rel_residual(oracle.divergence(u, v, w, g), gp, g) <= 1e-10
+    assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
