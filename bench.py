@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
 BYTES_PER_CELL = {
     "fp64": {"xfwd": 32, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "grad": 56},
     "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 12, "resid_xfwd": 20,
-                    "resid_norm": 16, "xinv_acc": 20, "grad": 56},
+                    "resid": 20, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 20, "grad": 56},
 }
 
 

@@ -21,9 +21,11 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "resid_norm", "", "", "", ""};
+    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "", ""};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
+constexpr int K_RESID_PAIRS = 12;
+constexpr int K_XFWD_R = 13;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -112,6 +114,24 @@ long xblocks(const fsei_plan* p) {
     const long nl = 2L * nseq_x(p);
     return ((long)p->ny * p->nz + nl - 1) / nl;
 }
+
+// Gradient kernel selection: 0 = one row per workgroup, one cell pair per
+// lane (nx even, <= 512, ny % 8 == 0); 1 = tiles of 8 rows, cell pairs;
+// 2 = one row per workgroup, one cell per lane.  FSEI_GRAD_CFG overrides the
+// default (0) for measurement; each falls back to 2 where it does not apply.
+int grad_cfg() {
+    static int v = [] {
+        const char* e = getenv("FSEI_GRAD_CFG");
+        return e ? atoi(e) : 0;
+    }();
+    return v;
+}
+
+// pair kernels (gradient, residual norm): lanes own two adjacent x-cells,
+// workgroups kPairRows rows of one plane
+constexpr int kPairRows = 8;
+bool pair_tiles(const fsei_plan* p) { return p->nx % 2 == 0 && p->ny % kPairRows == 0; }
+bool aligned16(const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; }
 
 // the fixed-length x kernels (NF = 512) need every tile of rows full and
 // inside one z-plane
@@ -426,7 +446,70 @@ void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoin
         a.gk = tab<TIO>(p, T_GAM_ADJ);
     }
     Timed t(p, K_GRAD);
+    const bool al = aligned16(u) && aligned16(v) && aligned16(w) && aligned16(pr);
+    if (grad_cfg() == 0 && p->nx % 2 == 0 && p->nx <= 512 && p->ny % 8 == 0 && al) {
+        const dim3 grid((unsigned)((long)p->ny * p->nz));
+        const int np = p->nx / 2;
+        if (np > 128)
+            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256>), grid, dim3(256), 0, S(p), a);
+        else if (np > 64)
+            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128>), grid, dim3(128), 0, S(p), a);
+        else
+            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64>), grid, dim3(64), 0, S(p), a);
+        return;
+    }
+    if (grad_cfg() == 1 && pair_tiles(p) && al) {
+        const dim3 grid((unsigned)((long)(p->ny / kPairRows) * p->nz));
+        const int np = p->nx / 2;
+        if (np >= 256)
+            hipLaunchKernelGGL((k_grad_pairs<TIO, TP, 256, kPairRows>), grid, dim3(256), 0, S(p), a);
+        else if (np > 64)
+            hipLaunchKernelGGL((k_grad_pairs<TIO, TP, 128, kPairRows>), grid, dim3(128), 0, S(p), a);
+        else
+            hipLaunchKernelGGL((k_grad_pairs<TIO, TP, 64, kPairRows>), grid, dim3(64), 0, S(p), a);
+        return;
+    }
     hipLaunchKernelGGL((k_grad<TIO, TP>), dim3((unsigned)((long)p->ny * p->nz)), dim3(256), 0, S(p), a);
+}
+
+// FP64 residual pass of the refinement (partials of sum r^2, sum r; with
+// out32, also r in FP32); returns the number of partials written
+long launch_resid_pairs(fsei_plan* p, const double* f, const double* pr, float* out32) {
+    ResArgs a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.bcy = p->bcy;
+    a.f = f;
+    a.p = pr;
+    a.idx2 = 1.0 / (p->dx * p->dx);
+    a.idy2 = 1.0 / (p->dy * p->dy);
+    a.za = tab<double>(p, T_ZA);
+    a.zc = tab<double>(p, T_ZC);
+    a.scal = scalars(p);
+    a.partials = partials(p);
+    a.out = out32;
+    const long nb = (long)(p->ny / kPairRows) * p->nz;
+    const dim3 grid((unsigned)nb);
+    const int np = p->nx / 2;
+    Timed t(p, out32 ? K_RESID_PAIRS : K_RESNORM);
+    if (out32) {
+        if (np >= 256)
+            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, true>), grid, dim3(256), 0, S(p), a);
+        else if (np > 64)
+            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, true>), grid, dim3(128), 0, S(p), a);
+        else
+            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, true>), grid, dim3(64), 0, S(p), a);
+    } else {
+        if (np >= 256)
+            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, false>), grid, dim3(256), 0, S(p), a);
+        else if (np > 64)
+            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, false>), grid, dim3(128), 0, S(p), a);
+        else
+            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, false>), grid, dim3(64), 0, S(p), a);
+    }
+    return nb;
 }
 
 template <typename TI, typename TO>
@@ -475,10 +558,11 @@ fsei_status read_scalars(fsei_plan* p, double* host, int n) {
 // sums of the last xfwd pass with partials (sum v^2, sum v, sum dz_k v) into
 // scalars[off..off+2]; with `vmean`, also scalars[0] = the V-mean of v,
 // sum dz_k v / (nx ny lz)
-void reduce_partials(fsei_plan* p, int off, bool vmean = false) {
+void reduce_partials(fsei_plan* p, int off, bool vmean = false, long nblk = -1) {
     Timed t(p, K_NORM);
     const double scale = 1.0 / ((double)p->nx * (double)p->ny * p->lz);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, S(p), (const double*)partials(p), (int)xblocks(p),
+    if (nblk < 0) nblk = xblocks(p);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, S(p), (const double*)partials(p), (int)nblk,
                        scalars(p) + off, vmean ? scalars(p) : nullptr, scale);
 }
 
@@ -527,8 +611,9 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     double rel = -1.0;
     bool converged = false;
     bool measured = false;   // rel belongs to the current iterate
+    long nres = -1;   // partials of the last residual pass (-1: the xfwd tiles)
     auto residual_norm = [&]() -> fsei_status {
-        reduce_partials(p, 1);   // scalars[1..3]: sum r^2, sum r, 0
+        reduce_partials(p, 1, false, nres);   // scalars[1..3]: sum r^2, sum r, 0
         double h[8];
         fsei_status st = read_scalars(p, h, 8);
         if (st != FSEI_OK) return st;
@@ -538,8 +623,34 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         return FSEI_OK;
     };
     // residual of the first solve, transformed for the first correction
-    r.out = w32;
-    launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+    // Residual passes.  With the pair tiling: the FP64 residual kernel
+    // (norm partials, and r in FP32 when a correction follows) plus an FP32
+    // x transform of r in place; otherwise the x-forward kernel with the
+    // residual stencil as its prologue (no output for a norm-only pass).
+    const bool pairs = pair_tiles(p) && aligned16(f64) && aligned16(p64) && aligned16(w32);
+    auto norm_pass = [&]() {
+        if (pairs) {
+            nres = launch_resid_pairs(p, f64, p64, nullptr);
+        } else {
+            r.out = nullptr;
+            nres = -1;
+            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
+        }
+    };
+    auto resid_pass = [&]() {
+        if (pairs) {
+            nres = launch_resid_pairs(p, f64, p64, w32);
+            XFwdArgs<float, float> t{};
+            t.src = w32;
+            t.out = w32;
+            launch_xfwd<float, float, PRO_SRC>(p, t, K_XFWD_R);
+        } else {
+            r.out = w32;
+            nres = -1;
+            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+        }
+    };
+    resid_pass();
     if (p->rtol > 0.0) {
         fsei_status st = residual_norm();
         if (st != FSEI_OK) return st;
@@ -553,20 +664,15 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         measured = false;
         if (p->rtol > 0.0) {
             // convergence check of the corrected iterate: norm only, no transform
-            r.out = nullptr;
-            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
+            norm_pass();
             fsei_status st = residual_norm();
             if (st != FSEI_OK) return st;
             if (converged) break;
         }
-        if (it < p->max_iter) {
-            r.out = w32;   // residual again, transformed for the next correction
-            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
-        }
+        if (it < p->max_iter) resid_pass();   // residual again, transformed for the next correction
     }
     if (info != nullptr && !measured) {
-        r.out = nullptr;
-        launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
+        norm_pass();
         fsei_status st = residual_norm();
         if (st != FSEI_OK) return st;
     }

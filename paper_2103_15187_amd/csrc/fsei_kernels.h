@@ -612,6 +612,216 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs<TIO, TP> a) {
     }
 }
 
+// Pair kernels: the same gradient correction with every lane owning two
+// adjacent x-cells (one 16-byte FP64 / 8-byte FP32 access per field), on
+// tiles of RJ rows of one z-plane.  Tiles go (row tile, plane) with the plane
+// fastest, so the k-1 rows of p were read by the previous workgroup on the
+// same XCD; the j-1 row comes from the lane's previous row in registers.
+// Launched when nx is even, ny % RJ == 0 and all fields are 16-byte aligned.
+template <typename TIO, typename TP, int NT, int RJ>
+__global__ __launch_bounds__(NT) void k_grad_pairs(GradArgs<TIO, TP> a) {
+    using V = typename Vec2T<TIO>::type;
+    using VP = typename Vec2T<TP>::type;
+    constexpr int RB = 4;   // rows per batch: all loads of a batch are issued before the first store
+    static_assert(RJ % RB == 0, "whole batches");
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int jt = b / nz;
+    const int k = b - jt * nz;
+    const int j0 = jt * RJ;
+    const size_t nxy = (size_t)nx * ny;
+    const TP* __restrict__ pk = a.p + (size_t)k * nxy;
+    const TP* __restrict__ pkm = (k > 0) ? pk - nxy : pk;   // unused at k = 0
+    TIO* __restrict__ u = a.u + (size_t)k * nxy;
+    TIO* __restrict__ v = a.v + (size_t)k * nxy;
+    TIO* __restrict__ w = a.w + (size_t)k * nxy;
+    const TIO bk = a.bk[k], gk = a.gk[k];
+    const bool wallx = a.bcx == FSEI_BC_WALL, wally = a.bcy == FSEI_BC_WALL;
+    // row j0 - 1 (periodic wrap; at a wall the v faces of row 0 are written 0)
+    const int jprev = (j0 > 0) ? j0 - 1 : ny - 1;
+    for (int c = threadIdx.x; 2 * c < nx; c += NT) {
+        const unsigned i = 2u * (unsigned)c;
+        const unsigned im = (i > 0) ? i - 1 : (unsigned)nx - 1;
+        VP prev = *reinterpret_cast<const VP*>(pk + (size_t)jprev * nx + i);
+#pragma unroll
+        for (int l0 = 0; l0 < RJ; l0 += RB) {
+            VP pc[RB], pz[RB];
+            TP pxm[RB];
+            V uo[RB], vo[RB], wo[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const size_t ro = (size_t)(j0 + l0 + r) * nx;
+                pc[r] = *reinterpret_cast<const VP*>(pk + ro + i);
+                pxm[r] = pk[ro + im];
+                pz[r] = *reinterpret_cast<const VP*>(pkm + ro + i);
+                uo[r] = *reinterpret_cast<const V*>(u + ro + i);
+                vo[r] = *reinterpret_cast<const V*>(v + ro + i);
+                wo[r] = *reinterpret_cast<const V*>(w + ro + i);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int j = j0 + l0 + r;
+                const size_t ro = (size_t)j * nx;
+                const VP pp = (r == 0) ? prev : pc[r > 0 ? r - 1 : 0];
+                V un, vn, wn;
+                un.x = (wallx && i == 0) ? (TIO)0 : uo[r].x + a.cx * ((TIO)pc[r].x - (TIO)pxm[r]);
+                un.y = uo[r].y + a.cx * ((TIO)pc[r].y - (TIO)pc[r].x);
+                const bool v0 = wally && j == 0;
+                vn.x = v0 ? (TIO)0 : vo[r].x + a.cy * ((TIO)pc[r].x - (TIO)pp.x);
+                vn.y = v0 ? (TIO)0 : vo[r].y + a.cy * ((TIO)pc[r].y - (TIO)pp.y);
+                wn.x = (k == 0) ? (TIO)0 : wo[r].x + a.sw * (bk * (TIO)pc[r].x - gk * (TIO)pz[r].x);
+                wn.y = (k == 0) ? (TIO)0 : wo[r].y + a.sw * (bk * (TIO)pc[r].y - gk * (TIO)pz[r].y);
+                *reinterpret_cast<V*>(u + ro + i) = un;
+                *reinterpret_cast<V*>(v + ro + i) = vn;
+                *reinterpret_cast<V*>(w + ro + i) = wn;
+            }
+            prev = pc[RB - 1];
+        }
+    }
+}
+
+// One x-row per workgroup, one cell pair per lane (NT >= nx / 2): the
+// simplest streaming shape, which runs closest to the HBM ceiling.  Rows in
+// tiles of GJ rows, plane by plane inside a tile (as k_grad).
+template <typename TIO, typename TP, int NT>
+__global__ __launch_bounds__(NT) void k_grad_row2(GradArgs<TIO, TP> a) {
+    using V = typename Vec2T<TIO>::type;
+    using VP = typename Vec2T<TP>::type;
+    constexpr int GJ = 8;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int nx = a.nx, ny = a.ny;
+    const int per = a.nz * GJ;
+    const int jt = b / per;
+    const int rem = b - jt * per;
+    const int k = rem / GJ;
+    const int j = jt * GJ + (rem - k * GJ);
+    const unsigned i = 2u * threadIdx.x;
+    if (i >= (unsigned)nx) return;
+    const size_t nxy = (size_t)nx * ny;
+    const size_t ro = (size_t)k * nxy + (size_t)j * nx;
+    const TP* __restrict__ pr = a.p + ro;
+    const TP* __restrict__ py = (j > 0) ? pr - nx : pr + (size_t)(ny - 1) * nx;   // j-1, wrapped
+    const TP* __restrict__ pz = (k > 0) ? pr - nxy : pr;                           // unused at k = 0
+    const unsigned im = (i > 0) ? i - 1 : (unsigned)nx - 1;
+    const VP pc = *reinterpret_cast<const VP*>(pr + i);
+    const TP pxm = pr[im];
+    const VP pyv = *reinterpret_cast<const VP*>(py + i);
+    const VP pzv = *reinterpret_cast<const VP*>(pz + i);
+    TIO* __restrict__ u = a.u + ro;
+    TIO* __restrict__ v = a.v + ro;
+    TIO* __restrict__ w = a.w + ro;
+    const V uo = *reinterpret_cast<const V*>(u + i);
+    const V vo = *reinterpret_cast<const V*>(v + i);
+    const V wo = *reinterpret_cast<const V*>(w + i);
+    const TIO bk = a.bk[k], gk = a.gk[k];
+    V un, vn, wn;
+    un.x = (a.bcx == FSEI_BC_WALL && i == 0) ? (TIO)0 : uo.x + a.cx * ((TIO)pc.x - (TIO)pxm);
+    un.y = uo.y + a.cx * ((TIO)pc.y - (TIO)pc.x);
+    const bool v0 = a.bcy == FSEI_BC_WALL && j == 0;
+    vn.x = v0 ? (TIO)0 : vo.x + a.cy * ((TIO)pc.x - (TIO)pyv.x);
+    vn.y = v0 ? (TIO)0 : vo.y + a.cy * ((TIO)pc.y - (TIO)pyv.y);
+    wn.x = (k == 0) ? (TIO)0 : wo.x + a.sw * (bk * (TIO)pc.x - gk * (TIO)pzv.x);
+    wn.y = (k == 0) ? (TIO)0 : wo.y + a.sw * (bk * (TIO)pc.y - gk * (TIO)pzv.y);
+    *reinterpret_cast<V*>(u + i) = un;
+    *reinterpret_cast<V*>(v + i) = vn;
+    *reinterpret_cast<V*>(w + i) = wn;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 residual of the refinement, r = (f - mean) - L p: per-block
+// (sum r^2, sum r, 0) partials and, with WRITE, r rounded to FP32 for the
+// next correction solve.  Same pair tiling as k_grad_pairs; the j-1 / j+1
+// rows of p rotate through registers.
+// ---------------------------------------------------------------------------
+struct ResArgs {
+    int nx, ny, nz, bcx, bcy;
+    const double* f;
+    const double* p;
+    double idx2, idy2;
+    const double* za;
+    const double* zc;
+    const double* scal;   // scal[0] = removed mean
+    double* partials;
+    float* out;           // WRITE: the residual in FP32 (input of the next correction)
+};
+
+template <int NT, int RJ, bool WRITE>
+__global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs a) {
+    constexpr int RB = 4;   // rows per load batch
+    static_assert(RJ % RB == 0, "whole batches");
+    __shared__ double sred[3 * (NT / 64)];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int jt = b / nz;
+    const int k = b - jt * nz;
+    const int j0 = jt * RJ;
+    const size_t nxy = (size_t)nx * ny;
+    const double* __restrict__ pk = a.p + (size_t)k * nxy;
+    const double* __restrict__ pkm = (k > 0) ? pk - nxy : pk;
+    const double* __restrict__ pkp = (k + 1 < nz) ? pk + nxy : pk;
+    const double* __restrict__ fk = a.f + (size_t)k * nxy;
+    const double czm = (k > 0) ? a.za[k] : 0.0, czp = (k + 1 < nz) ? a.zc[k] : 0.0;
+    const bool hzm = k > 0, hzp = k + 1 < nz;
+    const bool pery = a.bcy == FSEI_BC_PERIODIC, perx = a.bcx == FSEI_BC_PERIODIC;
+    const double mean = a.scal[0];
+    double ss = 0.0, s1 = 0.0;
+    for (int c = threadIdx.x; 2 * c < nx; c += NT) {
+        const unsigned i = 2u * (unsigned)c;
+        // x neighbours of the pair: i - 1 and i + 2 (wrapped)
+        const unsigned im = (i > 0) ? i - 1 : (unsigned)nx - 1;
+        const unsigned ip = (i + 2 < (unsigned)nx) ? i + 2 : 0u;
+        const bool him = (i > 0) || perx, hip = (i + 2 < (unsigned)nx) || perx;
+        const int jm0 = (j0 > 0) ? j0 - 1 : ny - 1;
+        double2 pm = *reinterpret_cast<const double2*>(pk + (size_t)jm0 * nx + i);
+        double2 pc = *reinterpret_cast<const double2*>(pk + (size_t)j0 * nx + i);
+#pragma unroll
+        for (int l0 = 0; l0 < RJ; l0 += RB) {
+            double2 pn[RB], pzm[RB], pzp[RB], fc[RB];
+            double pxm[RB], pxp[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int j = j0 + l0 + r;
+                const size_t ro = (size_t)j * nx;
+                const int jn = (j + 1 < ny) ? j + 1 : 0;
+                pn[r] = *reinterpret_cast<const double2*>(pk + (size_t)jn * nx + i);
+                pxm[r] = pk[ro + im];
+                pxp[r] = pk[ro + ip];
+                pzm[r] = *reinterpret_cast<const double2*>(pkm + ro + i);
+                pzp[r] = *reinterpret_cast<const double2*>(pkp + ro + i);
+                fc[r] = *reinterpret_cast<const double2*>(fk + ro + i);
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int j = j0 + l0 + r;
+                const bool hym = (j > 0) || pery, hyp = (j + 1 < ny) || pery;
+                // cell i: x neighbours i+1 (= pc.y) and i-1; cell i+1: i+2 and i
+                const double lx0 = (pc.y - pc.x) + (him ? pxm[r] - pc.x : 0.0);
+                const double lx1 = (hip ? pxp[r] - pc.y : 0.0) + (pc.x - pc.y);
+                const double ly0 = (hyp ? pn[r].x - pc.x : 0.0) + (hym ? pm.x - pc.x : 0.0);
+                const double ly1 = (hyp ? pn[r].y - pc.y : 0.0) + (hym ? pm.y - pc.y : 0.0);
+                const double lz0 = (hzp ? czp * (pzp[r].x - pc.x) : 0.0) + (hzm ? czm * (pzm[r].x - pc.x) : 0.0);
+                const double lz1 = (hzp ? czp * (pzp[r].y - pc.y) : 0.0) + (hzm ? czm * (pzm[r].y - pc.y) : 0.0);
+                const double r0 = (fc[r].x - mean) - (lx0 * a.idx2 + ly0 * a.idy2 + lz0);
+                const double r1 = (fc[r].y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1);
+                ss += r0 * r0 + r1 * r1;
+                s1 += r0 + r1;
+                if constexpr (WRITE)
+                    *reinterpret_cast<float2*>(a.out + (size_t)k * nxy + (size_t)j * nx + i) =
+                        make_float2((float)r0, (float)r1);
+                pm = pc;
+                pc = pn[r];
+            }
+        }
+    }
+    double s2 = 0.0;
+    block_sum3<NT>(ss, s1, s2, sred);
+    if (threadIdx.x == 0) {
+        a.partials[3 * blockIdx.x] = ss;
+        a.partials[3 * blockIdx.x + 1] = s1;
+        a.partials[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
 // deterministic sum of the per-block partial triples (one workgroup of 1024
 // threads, 8 blocks' triples in flight per thread, fixed summation order);
 // optionally also mean_out = (third sum) * mean_scale

@@ -57,7 +57,10 @@ void compute_layout(fsei_plan_impl* p) {
     }
     p->nlist = (int)p->list_host.size();
     const long nseq = x_nseq(p->nx);
-    p->n_partials = (size_t)(((long)p->ny * p->nz + 2 * nseq - 1) / (2 * nseq));
+    // one partial triple per x-forward tile, or per 8-row tile of the
+    // residual-norm pass, whichever is more
+    p->n_partials = (size_t)std::max(((long)p->ny * p->nz + 2 * nseq - 1) / (2 * nseq),
+                                     (long)((p->ny + 7) / 8) * p->nz);
 
     size_t off = 0;
     p->ws_tab_d = off;

@@ -242,7 +242,7 @@ struct Vec2T<float> {
 // x forward: prologue (divergence / transposed gradient / residual / copy)
 // fused with the forward x transform
 // ---------------------------------------------------------------------------
-enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3 };
+enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3, PRO_SRC = 4 };
 
 template <typename TI, typename TO>
 struct XFwdArgs {
@@ -254,6 +254,7 @@ struct XFwdArgs {
     const TI* w;
     const TI* gp;       // adjoint: dLoss/dp or null
     const double* f;    // COPY (double input) and RESID
+    const TI* src;      // SRC: input of the prologue's own type
     const double* p;    // RESID
     TI alpha, beta, idx, idy;
     const TI* zeta;     // coefficient of w_{k+1}
@@ -283,6 +284,8 @@ __device__ __forceinline__ TI x_prologue(const XFwdArgs<TI, TO>& a, size_t base,
     const int nxy = nx * ny;
     if constexpr (PRO == PRO_COPY) {
         return (TI)a.f[base + o];
+    } else if constexpr (PRO == PRO_SRC) {
+        return a.src[base + o];
     } else if constexpr (PRO == PRO_RESID) {
         const double* __restrict__ p = a.p + base;
         const double pc = p[o];
@@ -328,6 +331,8 @@ __device__ __forceinline__ TI x_prologue_row(const XFwdArgs<TI, TO>& a, size_t r
                                              const ColNb& cn) {
     if constexpr (PRO == PRO_COPY) {
         return (TI)a.f[ro + cn.i];
+    } else if constexpr (PRO == PRO_SRC) {
+        return a.src[ro + cn.i];
     } else if constexpr (PRO == PRO_RESID) {
         const double* __restrict__ p = a.p + ro;
         const double pc = p[cn.i];
