@@ -57,7 +57,9 @@ typedef enum {
     FSEI_ERR_GRID = -3,          /* zc not finite or not strictly increasing; dx or dy <= 0 */
     FSEI_ERR_WORKSPACE = -4,     /* no workspace set, or smaller than fsei_plan_workspace_size, or not 256-B aligned */
     FSEI_ERR_HIP = -5,           /* a HIP runtime call or kernel launch failed */
-    FSEI_ERR_NOT_CONVERGED = -6, /* FP32_REFINE did not reach rtol in max_iter corrections; outputs hold the last iterate */
+    FSEI_ERR_NOT_CONVERGED = -6, /* FP32_REFINE did not reach rtol (max_iter corrections done, or the
+                                    residual stopped decreasing: fsei_info.floor_reached); outputs hold
+                                    the last iterate */
     FSEI_ERR_PRECISION = -7      /* entry point does not match the plan's precision mode */
 } fsei_status;
 
@@ -78,6 +80,9 @@ typedef struct {
     int iterations;            /* FP32_REFINE correction solves done (0 otherwise) */
     double rel_residual;       /* ||f - L p||_2 / ||f||_2 when measured (FP32_REFINE), else -1 */
     double rhs_vmean_removed;  /* volume-weighted mean of f removed before the solve */
+    int floor_reached;         /* FP32_REFINE: 1 when the refinement stopped because a correction
+                                  no longer halved the residual (the FP64 rounding floor of this
+                                  right-hand side lies above rtol), else 0 */
 } fsei_info;
 
 /* Create a plan (host only; no device memory, no HIP call).

@@ -608,8 +608,9 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     r.scal = scalars(p);
     r.partials = partials(p);
     int it = 0;
-    double rel = -1.0;
+    double rel = -1.0, rel_prev = -1.0;
     bool converged = false;
+    bool floor = false;      // a correction no longer halved the residual
     bool measured = false;   // rel belongs to the current iterate
     long nres = -1;   // partials of the last residual pass (-1: the xfwd tiles)
     auto residual_norm = [&]() -> fsei_status {
@@ -617,9 +618,13 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         double h[8];
         fsei_status st = read_scalars(p, h, 8);
         if (st != FSEI_OK) return st;
+        rel_prev = rel;
         rel = rel_from(h);
         measured = true;
         converged = p->rtol > 0.0 && rel <= p->rtol;
+        // the FP64 residual cannot fall below the rounding floor of the
+        // stencil applied to this p: stop once a correction gains < 2x
+        floor = !converged && rel_prev >= 0.0 && rel > 0.5 * rel_prev;
         return FSEI_OK;
     };
     // residual of the first solve, transformed for the first correction
@@ -667,7 +672,7 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
             norm_pass();
             fsei_status st = residual_norm();
             if (st != FSEI_OK) return st;
-            if (converged) break;
+            if (converged || floor) break;
         }
         if (it < p->max_iter) resid_pass();   // residual again, transformed for the next correction
     }
@@ -683,6 +688,7 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         info->iterations = it;
         info->rel_residual = rel;
         info->rhs_vmean_removed = h[0];
+        info->floor_reached = floor ? 1 : 0;
     }
     fsei_status st = check_hip();
     if (st != FSEI_OK) return st;
@@ -762,6 +768,7 @@ fsei_status fsei_poisson_solve(fsei_plan* p, const double* f, double* out, fsei_
         info->iterations = 0;
         info->rel_residual = -1.0;
         info->rhs_vmean_removed = h[0];
+        info->floor_reached = 0;
     }
     return FSEI_OK;
 }
@@ -799,6 +806,7 @@ fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* 
         info->iterations = 0;
         info->rel_residual = -1.0;
         info->rhs_vmean_removed = h[0];
+        info->floor_reached = 0;
     }
     return FSEI_OK;
 }

@@ -41,7 +41,7 @@ class FseiError(RuntimeError):
 
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("rhs_vmean_removed", ctypes.c_double)]
+                ("rhs_vmean_removed", ctypes.c_double), ("floor_reached", ctypes.c_int)]
 
 
 def lib():
@@ -105,7 +105,7 @@ class Plan:
     The workspace is a torch uint8 tensor on `device`."""
 
     def __init__(self, nx, ny, nz, bc, dx, dy, zc, precision=PREC_FP64, rtol=1e-10, max_iter=4,
-                 device="cuda"):
+                 device="cuda", accept_floor=False):
         import torch
         L = lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
@@ -121,6 +121,10 @@ class Plan:
                                           ctypes.byref(h)), "fsei_poisson_plan_create")
         self._h = h
         self.precision = precision
+        # FP32_REFINE: when the refinement stops at the FP64 rounding floor of
+        # the right-hand side above rtol, return the iterate (with a warning)
+        # instead of raising FseiError(FSEI_ERR_NOT_CONVERGED)
+        self.accept_floor = bool(accept_floor)
         _check(L.fsei_plan_set_precision(h, precision, float(rtol), int(max_iter)), "fsei_plan_set_precision")
         nbytes = ctypes.c_size_t()
         _check(L.fsei_plan_workspace_size(h, ctypes.byref(nbytes)), "fsei_plan_workspace_size")
@@ -158,6 +162,17 @@ class Plan:
             raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor of shape {self.shape}")
         return t
 
+    def _floor_ok(self):
+        return self.accept_floor and self.precision == PREC_FP32_REFINE
+
+    def _status(self, status, what, inf):
+        if status == -6 and self._floor_ok() and inf.floor_reached:
+            import warnings
+            warnings.warn(f"{what}: refinement stopped at the FP64 rounding floor, relative residual "
+                          f"{inf.rel_residual:.3e} (above rtol)", RuntimeWarning, stacklevel=3)
+            return
+        _check(status, what)
+
     # -- entry points ---------------------------------------------------------
     def poisson_solve(self, f, p=None, info=False):
         """p = L^+ f (double; p may be f for an in-place solve)."""
@@ -168,8 +183,9 @@ class Plan:
         p = self._field(p, torch.float64, "p")
         self._stream()
         inf = Info()
-        _check(lib().fsei_poisson_solve(self._h, _ptr(f), _ptr(p), ctypes.byref(inf) if info else None),
-               "fsei_poisson_solve")
+        want = info or self._floor_ok()
+        self._status(lib().fsei_poisson_solve(self._h, _ptr(f), _ptr(p), ctypes.byref(inf) if want else None),
+                     "fsei_poisson_solve", inf)
         return (p, _info_dict(inf)) if info else p
 
     def project(self, u, v, w, p=None, dt=1.0, info=False, want_p=True):
@@ -189,8 +205,9 @@ class Plan:
         p = self._field(p, torch.float64, "p")
         self._stream()
         inf = Info()
-        _check(lib().fsei_project(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(p), float(dt),
-                                  ctypes.byref(inf) if info else None), "fsei_project")
+        want = info or self._floor_ok()
+        self._status(lib().fsei_project(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(p), float(dt),
+                                        ctypes.byref(inf) if want else None), "fsei_project", inf)
         return (p, _info_dict(inf)) if info else p
 
     def project_backward(self, gu, gv, gw, gp=None, dt=1.0):
@@ -230,7 +247,7 @@ class Plan:
 
 def _info_dict(inf):
     return {"iterations": inf.iterations, "rel_residual": inf.rel_residual,
-            "rhs_vmean_removed": inf.rhs_vmean_removed}
+            "rhs_vmean_removed": inf.rhs_vmean_removed, "floor_reached": bool(inf.floor_reached)}
 
 
 def _autograd_fn():
