@@ -16,6 +16,7 @@ Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,6 +28,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_512x512x768.json")
+
+# Kernel that each timing slot launches at the 512 x 512 x 768 workload (the
+# hardware-counter summary is keyed by kernel name)
+SLOT_KERNEL = {
+    "fp64": {"xfwd": "k_xfwd<double, double, 1, 2048, 256, 512>", "yfwd": "k_yfwd<double, 4096, 512, 512>",
+             "zsolve": "k_zsolve2<double, double, 16, 24, 512>", "yinv": "k_yinv<double, 4096, 512, 512>",
+             "xinv": "k_xinv<double, double, 0, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256>"},
+    "fp32_refine": {"xfwd": "k_xfwd<double, float, 1, 2048, 256, 512>", "yfwd": "k_yfwd<float, 8192, 1024, 512>",
+                    "zsolve": "k_zsolve2<float, float, 32, 24, 1024>", "yinv": "k_yinv<float, 8192, 1024, 512>",
+                    "xinv": "k_xinv<float, double, 0, 2048, 256, 512>", "xinv_acc": "k_xinv<float, double, 1, 2048, 256, 512>",
+                    "resid": "k_resid_pairs<256, 8, true>", "resid_norm": "k_resid_pairs<256, 8, false>",
+                    "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256>"},
+}
 
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:
 # every operand read once, every result written once).
@@ -102,6 +117,34 @@ def divergence_max(u, v, w, spec, torch):
     return d.abs().max().item()
 
 
+def kernel_source_hash():
+    """sha256 of the HIP/C++ sources of the library (the counters in the
+    traffic summary belong to the sources they were measured on)."""
+    csrc = os.path.join(ROOT, "paper_2103_15187_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in sorted(os.listdir(csrc)):
+        if fn.endswith((".hip", ".h", ".cpp")):
+            h.update(fn.encode())
+            with open(os.path.join(csrc, fn), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(mode, slot):
+    """Calibrated HBM bytes per launch of the slot's kernel from the committed
+    counter summary, or None when there is none for it or the sources have
+    changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(SLOT_KERNEL.get(mode, {}).get(slot, ""))
+    return None if k is None else round(k["fetch_bytes"] + k["write_bytes"])
+
+
 def roofline_for(mode, res, ncells):
     """Dominant kernel (largest total time) and its achieved algorithmic
     bandwidth over the timed region."""
@@ -113,8 +156,69 @@ def roofline_for(mode, res, ncells):
     bytes_per_launch = bpc[name] * ncells
     achieved = bytes_per_launch / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mode, name),
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+
+def _short_kernel(name):
+    return name.split("(")[0].replace("void ", "").replace("fsei::dev::", "").strip()
+
+
+def summarize_profiles(d, cmd_trace, cmd_pmc):
+    """Turn the rocprofv3 outputs under `d` (prof/, pmc_FETCH_SIZE/,
+    pmc_WRITE_SIZE/) into the committed summaries under profiles/."""
+    import csv
+    out = os.path.join(ROOT, "profiles")
+    rows = list(csv.DictReader(open(os.path.join(d, "prof", "c3_kernel_stats.csv"))))
+    md = ["# Kernel trace: projection, 512x512x768 walls tanh 2.5 (FP32+refine and FP64 modes)", "",
+          "Command (run from the repository root on one MI355X):", "", "```", cmd_trace, "```", "",
+          "| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        name = _short_kernel(r["Name"])
+        if len(name) > 70:
+            name = name[:70] + "..."
+        md.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                  f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    with open(os.path.join(out, "projection_c3_512x512x768_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    # hardware byte counters (KiB per dispatch), calibrated on torch.neg over
+    # one FP64 field of the workload (reads and writes 8 B per cell)
+    spec_cells = 512 * 512 * 768
+    vals = {}
+    for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+        for r in csv.DictReader(open(os.path.join(d, f"pmc_{ctr}", "c3_counter_collection.csv"))):
+            full = r["Kernel_Name"]
+            key = "CALIB" if "neg_kernel" in full else _short_kernel(full)
+            vals.setdefault((key, ctr), []).append(float(r["Counter_Value"]) * 1024.0)
+    cal = {c: 8.0 * spec_cells / (sum(vals[("CALIB", c)]) / len(vals[("CALIB", c)]))
+           for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    kern = {}
+    for (key, ctr), v in vals.items():
+        if key == "CALIB" or not key.startswith("k_"):
+            continue
+        e = kern.setdefault(key, {"dispatches": len(v)})
+        e["fetch_bytes" if ctr == "FETCH_SIZE" else "write_bytes"] = sum(v) / len(v) * cal[ctr]
+    res = {"workload": "512x512x768 cells, walls, tanh 2.5", "source_sha256": kernel_source_hash(),
+           "command": cmd_pmc, "calibration": {"kernel": "torch.neg over one FP64 field (8 B read + 8 B written per cell)",
+                                               "fetch_factor": round(cal["FETCH_SIZE"], 4),
+                                               "write_factor": round(cal["WRITE_SIZE"], 4)},
+           "kernels": kern}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(res, fh, indent=1, sort_keys=True)
+    md = ["# HBM traffic per kernel launch: projection, 512x512x768 walls tanh 2.5", "",
+          "Commands (run from the repository root on one MI355X; one counter per run):", "", "```", cmd_pmc, "```", "",
+          f"Counters scaled by the reading of a plain streaming kernel of known size (torch.neg over one FP64 "
+          f"field, 8 B read + 8 B written per cell): FETCH_SIZE x{cal['FETCH_SIZE']:.3f}, "
+          f"WRITE_SIZE x{cal['WRITE_SIZE']:.3f}. Bytes per cell = bytes per launch / {spec_cells}.", "",
+          f"Kernel sources sha256: `{res['source_sha256']}`", "",
+          "| kernel | launches | read B/cell | write B/cell | total GB/launch |", "|---|---:|---:|---:|---:|"]
+    for key in sorted(kern):
+        e = kern[key]
+        md.append(f"| `{key[:70]}` | {e['dispatches']} | {e.get('fetch_bytes', 0) / spec_cells:.2f} | "
+                  f"{e.get('write_bytes', 0) / spec_cells:.2f} | "
+                  f"{(e.get('fetch_bytes', 0) + e.get('write_bytes', 0)) / 1e9:.3f} |")
+    with open(os.path.join(out, "hbm_traffic_c3_512x512x768.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
 
 
 def mode_summary(mode, res, ncells, steps):
@@ -177,7 +281,20 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also run torch.neg over one field (a plain streaming kernel of known size: "
                          "reads and writes 8 B per cell) to calibrate hardware byte counters")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="write profiles/ summaries from the rocprofv3 outputs under DIR and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize_profiles(
+            args.summarize,
+            "rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o c3 --output-format csv -- "
+            "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline",
+            "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_FETCH_SIZE -o c3 --output-format csv -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib\n"
+            "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_WRITE_SIZE -o c3 --output-format csv -- "
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib\n"
+            "python3 bench.py --summarize gpurun_out")
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs the projection on one GPU only; multi-GPU runs are not supported "
               "(the slab decomposition is a design note, not built)", file=sys.stderr)
