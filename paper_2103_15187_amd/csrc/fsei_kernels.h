@@ -35,6 +35,24 @@ namespace dev {
 // `transposed` solves T^T y = g through T^T = dz T dz^{-1} (scale by 1/dz_k on
 // load and by dz_k on store).
 // ---------------------------------------------------------------------------
+// Reciprocal for the tridiagonal sweeps: the hardware estimate refined by
+// Newton steps r <- r + r (1 - x r) (two in FP64, one in FP32), within a
+// few ulp of 1/x for the well-scaled pivots of these systems (|x| between
+// the smallest z coefficient and |lambda_x + lambda_y|).  The IEEE-exact
+// division the compiler emits otherwise is a chain of ten dependent
+// instructions on the critical path of every row.
+__device__ __forceinline__ double zrcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float zrcp(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <typename TS, typename TC>
 struct ZArgs {
     int nx, ny, nz, L, P, transposed, nlist;
@@ -124,7 +142,7 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
     for (int t = 0; t < L - 1; ++t) {
         const int k = s0 + t;
         const TC A = ta[k], C = tc[k], B = ZDIAG(k);
-        const TC r = (TC)1 / (B - A * cp);
+        const TC r = zrcp(B - A * cp);
         Rr[t] = r;
         dp = (F[t] - A * dp) * r;
         g = -A * g * r;
@@ -174,14 +192,14 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
             TC k1 = 0, k2 = 0, alm = 0, gam = 0, phm = 0, alp = 0, gap = 0, php = 0;
             if (p - s >= 0) {
                 const int id = me - s * TXL;
-                k1 = al / sh[1][id];
+                k1 = al * zrcp(sh[1][id]);
                 alm = sh[0][id];
                 gam = sh[2][id];
                 phm = sh[3][id];
             }
             if (p + s < P) {
                 const int id = me + s * TXL;
-                k2 = ga / sh[1][id];
+                k2 = ga * zrcp(sh[1][id]);
                 alp = sh[0][id];
                 gap = sh[2][id];
                 php = sh[3][id];
@@ -193,7 +211,7 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
         }
     }
     __syncthreads();
-    sh[0][me] = ph / be;   // chunk-end value x_{e(p)}
+    sh[0][me] = ph * zrcp(be);   // chunk-end value x_{e(p)}
     __syncthreads();
     const TC XR = sh[0][me];
     const TC XL = (p > 0) ? sh[0][me - TXL] : (TC)0;
@@ -302,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
         const TC A = ta[k], C = tc[k], B0 = tb[k], M = tm[k];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const TC r = (TC)1 / (B0 + sigma[h] * M - A * cp[h]);
+            const TC r = zrcp(B0 + sigma[h] * M - A * cp[h]);
             Rr[h][t] = r;
             dp[h] = (F[h][t] - A * dp[h]) * r;
             g[h] = -A * g[h] * r;
@@ -359,14 +377,14 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
                 TC k1 = 0, k2 = 0, alm = 0, gam = 0, phm = 0, alp = 0, gap = 0, php = 0;
                 if (p - s >= 0) {
                     const int id = 2 * (me - s * TXL2) + h;
-                    k1 = al[h] / sh[1][id];
+                    k1 = al[h] * zrcp(sh[1][id]);
                     alm = sh[0][id];
                     gam = sh[2][id];
                     phm = sh[3][id];
                 }
                 if (p + s < P) {
                     const int id = 2 * (me + s * TXL2) + h;
-                    k2 = ga[h] / sh[1][id];
+                    k2 = ga[h] * zrcp(sh[1][id]);
                     alp = sh[0][id];
                     gap = sh[2][id];
                     php = sh[3][id];
@@ -380,7 +398,7 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h) sh[0][2 * me + h] = ph[h] / be[h];
+    for (int h = 0; h < 2; ++h) sh[0][2 * me + h] = ph[h] * zrcp(be[h]);
     __syncthreads();
     TC XR[2], XL[2];
 #pragma unroll
