@@ -106,6 +106,7 @@ double* partials(const fsei_plan* p) { return reinterpret_cast<double*>((char*)p
 void* field1(const fsei_plan* p) { return (char*)p->ws + p->ws_field; }
 void* field2(const fsei_plan* p) { return (char*)p->ws + p->ws_field2; }
 void* field3(const fsei_plan* p) { return (char*)p->ws + p->ws_field3; }
+void* field4(const fsei_plan* p) { return (char*)p->ws + p->ws_field4; }
 int* zlist(const fsei_plan* p) { return reinterpret_cast<int*>((char*)p->ws + p->ws_list); }
 
 int nseq_x(const fsei_plan* p) { return x_nseq(p->nx); }
@@ -166,8 +167,9 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
 }
 
 template <typename T, typename TP, int EPI>
-void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot) {
+void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add32 = nullptr) {
     XInvArgs<T, TP> a{};
+    a.add32 = add32;
     a.nx = p->nx;
     a.ny = p->ny;
     a.nz = p->nz;
@@ -474,8 +476,9 @@ void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoin
 
 // FP64 residual pass of the refinement (partials of sum r^2, sum r; with
 // out32, also r in FP32); returns the number of partials written
-long launch_resid_pairs(fsei_plan* p, const double* f, const double* pr, float* out32) {
-    ResArgs a{};
+template <typename TPP>
+long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr, float* out32) {
+    ResArgs<TPP> a{};
     a.nx = p->nx;
     a.ny = p->ny;
     a.nz = p->nz;
@@ -496,18 +499,18 @@ long launch_resid_pairs(fsei_plan* p, const double* f, const double* pr, float* 
     Timed t(p, out32 ? K_RESID_PAIRS : K_RESNORM);
     if (out32) {
         if (np >= 256)
-            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, true>), grid, dim3(256), 0, S(p), a);
+            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, true, TPP>), grid, dim3(256), 0, S(p), a);
         else if (np > 64)
-            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, true>), grid, dim3(128), 0, S(p), a);
+            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, true, TPP>), grid, dim3(128), 0, S(p), a);
         else
-            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, true>), grid, dim3(64), 0, S(p), a);
+            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, true, TPP>), grid, dim3(64), 0, S(p), a);
     } else {
         if (np >= 256)
-            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, false>), grid, dim3(256), 0, S(p), a);
+            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, false, TPP>), grid, dim3(256), 0, S(p), a);
         else if (np > 64)
-            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, false>), grid, dim3(128), 0, S(p), a);
+            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, false, TPP>), grid, dim3(128), 0, S(p), a);
         else
-            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, false>), grid, dim3(64), 0, S(p), a);
+            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, false, TPP>), grid, dim3(64), 0, S(p), a);
     }
     return nb;
 }
@@ -589,7 +592,18 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     launch_y<float>(p, w32, false);
     launch_z<float>(p, w32, 0, false);
     launch_y<float>(p, w32, true);
-    launch_xinv<float, double, EPI_STORE>(p, w32, p64, K_XINV);
+    // With the pair tiling the first solve's pressure stays in FP32 (its
+    // error is FP32-level anyway; the residual is evaluated exactly in FP64
+    // from those values and the first correction writes p = p32 + delta in
+    // FP64), saving 4 bytes per cell in each of three passes.  Otherwise it is
+    // written to p64 directly.
+    float* p32 = static_cast<float*>(field4(p));
+    const bool pairs = pair_tiles(p) && aligned16(f64) && aligned16(p64) && aligned16(w32) && aligned16(p32);
+    if (pairs)
+        launch_xinv<float, float, EPI_STORE>(p, w32, p32, K_XINV);
+    else
+        launch_xinv<float, double, EPI_STORE>(p, w32, p64, K_XINV);
+    bool p_in_32 = pairs;   // the current iterate is p32 (before the first correction)
     const double N = (double)p->ncells();
     auto rel_from = [&](const double* h) {
         // ||f - mean||^2 = sum f^2 - 2 mean sum f + N mean^2; h[1] = sum r^2
@@ -632,10 +646,10 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     // (norm partials, and r in FP32 when a correction follows) plus an FP32
     // x transform of r in place; otherwise the x-forward kernel with the
     // residual stencil as its prologue (no output for a norm-only pass).
-    const bool pairs = pair_tiles(p) && aligned16(f64) && aligned16(p64) && aligned16(w32);
     auto norm_pass = [&]() {
         if (pairs) {
-            nres = launch_resid_pairs(p, f64, p64, nullptr);
+            nres = p_in_32 ? launch_resid_pairs(p, f64, (const float*)p32, nullptr)
+                           : launch_resid_pairs(p, f64, (const double*)p64, nullptr);
         } else {
             r.out = nullptr;
             nres = -1;
@@ -644,7 +658,8 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     };
     auto resid_pass = [&]() {
         if (pairs) {
-            nres = launch_resid_pairs(p, f64, p64, w32);
+            nres = p_in_32 ? launch_resid_pairs(p, f64, (const float*)p32, w32)
+                           : launch_resid_pairs(p, f64, (const double*)p64, w32);
             XFwdArgs<float, float> t{};
             t.src = w32;
             t.out = w32;
@@ -664,7 +679,12 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         launch_y<float>(p, w32, false);
         launch_z<float>(p, w32, 0, false);
         launch_y<float>(p, w32, true);
-        launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC);
+        if (p_in_32) {
+            launch_xinv<float, double, EPI_ADDF>(p, w32, p64, K_XINV_ACC, p32);   // p64 = p32 + delta
+            p_in_32 = false;
+        } else {
+            launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC);
+        }
         ++it;
         measured = false;
         if (p->rtol > 0.0) {
@@ -675,6 +695,15 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
             if (converged || floor) break;
         }
         if (it < p->max_iter) resid_pass();   // residual again, transformed for the next correction
+    }
+    if (p_in_32) {
+        // no correction ran (max_iter = 0, or the first solve already met
+        // rtol): the iterate is the FP32 first solve
+        const size_t n = p->ncells();
+        Timed t(p, K_XINV_ACC);
+        hipLaunchKernelGGL(k_widen, dim3((unsigned)std::min<size_t>((n + 255) / 256, 65536)), dim3(256), 0, S(p),
+                           (const float*)p32, p64, n);
+        p_in_32 = false;
     }
     if (info != nullptr && !measured) {
         norm_pass();

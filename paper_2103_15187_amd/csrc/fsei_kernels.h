@@ -751,10 +751,11 @@ __global__ __launch_bounds__(NT) void k_grad_row2(GradArgs<TIO, TP> a) {
 // next correction solve.  Same pair tiling as k_grad_pairs; the j-1 / j+1
 // rows of p rotate through registers.
 // ---------------------------------------------------------------------------
+template <typename TPP>
 struct ResArgs {
     int nx, ny, nz, bcx, bcy;
     const double* f;
-    const double* p;
+    const TPP* p;         // pressure iterate (FP64, or the first FP32 solve)
     double idx2, idy2;
     const double* za;
     const double* zc;
@@ -763,8 +764,15 @@ struct ResArgs {
     float* out;           // WRITE: the residual in FP32 (input of the next correction)
 };
 
-template <int NT, int RJ, bool WRITE>
-__global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs a) {
+// two adjacent values of T as a double2
+template <typename T>
+__device__ __forceinline__ double2 ld2d(const T* q) {
+    const auto v = *reinterpret_cast<const typename Vec2T<T>::type*>(q);
+    return make_double2((double)v.x, (double)v.y);
+}
+
+template <int NT, int RJ, bool WRITE, typename TPP>
+__global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
     constexpr int RB = 4;   // rows per load batch
     static_assert(RJ % RB == 0, "whole batches");
     __shared__ double sred[3 * (NT / 64)];
@@ -774,9 +782,9 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs a) {
     const int k = b - jt * nz;
     const int j0 = jt * RJ;
     const size_t nxy = (size_t)nx * ny;
-    const double* __restrict__ pk = a.p + (size_t)k * nxy;
-    const double* __restrict__ pkm = (k > 0) ? pk - nxy : pk;
-    const double* __restrict__ pkp = (k + 1 < nz) ? pk + nxy : pk;
+    const TPP* __restrict__ pk = a.p + (size_t)k * nxy;
+    const TPP* __restrict__ pkm = (k > 0) ? pk - nxy : pk;
+    const TPP* __restrict__ pkp = (k + 1 < nz) ? pk + nxy : pk;
     const double* __restrict__ fk = a.f + (size_t)k * nxy;
     const double czm = (k > 0) ? a.za[k] : 0.0, czp = (k + 1 < nz) ? a.zc[k] : 0.0;
     const bool hzm = k > 0, hzp = k + 1 < nz;
@@ -790,8 +798,8 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs a) {
         const unsigned ip = (i + 2 < (unsigned)nx) ? i + 2 : 0u;
         const bool him = (i > 0) || perx, hip = (i + 2 < (unsigned)nx) || perx;
         const int jm0 = (j0 > 0) ? j0 - 1 : ny - 1;
-        double2 pm = *reinterpret_cast<const double2*>(pk + (size_t)jm0 * nx + i);
-        double2 pc = *reinterpret_cast<const double2*>(pk + (size_t)j0 * nx + i);
+        double2 pm = ld2d(pk + (size_t)jm0 * nx + i);
+        double2 pc = ld2d(pk + (size_t)j0 * nx + i);
 #pragma unroll
         for (int l0 = 0; l0 < RJ; l0 += RB) {
             double2 pn[RB], pzm[RB], pzp[RB], fc[RB];
@@ -801,11 +809,11 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs a) {
                 const int j = j0 + l0 + r;
                 const size_t ro = (size_t)j * nx;
                 const int jn = (j + 1 < ny) ? j + 1 : 0;
-                pn[r] = *reinterpret_cast<const double2*>(pk + (size_t)jn * nx + i);
-                pxm[r] = pk[ro + im];
-                pxp[r] = pk[ro + ip];
-                pzm[r] = *reinterpret_cast<const double2*>(pkm + ro + i);
-                pzp[r] = *reinterpret_cast<const double2*>(pkp + ro + i);
+                pn[r] = ld2d(pk + (size_t)jn * nx + i);
+                pxm[r] = (double)pk[ro + im];
+                pxp[r] = (double)pk[ro + ip];
+                pzm[r] = ld2d(pkm + ro + i);
+                pzp[r] = ld2d(pkp + ro + i);
                 fc[r] = *reinterpret_cast<const double2*>(fk + ro + i);
             }
 #pragma unroll
@@ -838,6 +846,12 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs a) {
         a.partials[3 * blockIdx.x + 1] = s1;
         a.partials[3 * blockIdx.x + 2] = 0.0;
     }
+}
+
+// out = (double) in, n values (grid-stride)
+__global__ __launch_bounds__(256) void k_widen(const float* __restrict__ in, double* __restrict__ out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+        out[i] = (double)in[i];
 }
 
 // deterministic sum of the per-block partial triples (one workgroup of 1024

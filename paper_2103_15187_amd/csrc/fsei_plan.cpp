@@ -88,6 +88,9 @@ void compute_layout(fsei_plan_impl* p) {
     p->ws_field3 = off;
     p->ws_field3_bytes = refine ? N * sizeof(double) : 0;
     off = round_up(off + p->ws_field3_bytes, kAlign);
+    p->ws_field4 = off;
+    p->ws_field4_bytes = refine ? N * sizeof(float) : 0;
+    off = round_up(off + p->ws_field4_bytes, kAlign);
     p->ws_total = off;
 }
 

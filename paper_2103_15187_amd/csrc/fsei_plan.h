@@ -93,6 +93,7 @@ struct fsei_plan_impl {
     size_t ws_field = 0, ws_field_bytes = 0;       // main intermediate field
     size_t ws_field2 = 0, ws_field2_bytes = 0;     // second field (refine: FP32 work field)
     size_t ws_field3 = 0, ws_field3_bytes = 0;     // refine: FP64 pressure when the caller passes none
+    size_t ws_field4 = 0, ws_field4_bytes = 0;     // refine: FP32 pressure of the first solve
     size_t ws_list = 0, ws_list_bytes = 0;         // mode lines solved in FP64 by FP32 plans
     size_t ws_total = 0;
     size_t n_partials = 0;                          // per-block partial sums (triples)

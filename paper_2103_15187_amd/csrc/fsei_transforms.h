@@ -534,7 +534,7 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
 // x inverse: unnormalised inverse x transform of row pairs; writes (STORE)
 // or adds (ACC) the result into the output field
 // ---------------------------------------------------------------------------
-enum { EPI_STORE = 0, EPI_ACC = 1 };
+enum { EPI_STORE = 0, EPI_ACC = 1, EPI_ADDF = 2 };   // ADDF: out = add32 + result
 
 template <typename T, typename TP>
 struct XInvArgs {
@@ -542,6 +542,7 @@ struct XInvArgs {
     FftPlan fp;
     const T* in;
     TP* out;
+    const float* add32;   // EPI_ADDF: FP32 field added to the result
     const T* twc;
     const T* tws;
     const T* dctc;
@@ -622,12 +623,15 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
             const int i = threadIdx.x + c * NTHR;
             ln[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
         }
-        if constexpr (EPI == EPI_ACC) {
+        if constexpr (EPI == EPI_ACC || EPI == EPI_ADDF) {
             TP old[NL][CPR];
+            const float* __restrict__ add = (EPI == EPI_ADDF) ? a.add32 + base : nullptr;
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
-                for (int c = 0; c < CPR; ++c) old[l][c] = out[l * NF + threadIdx.x + c * NTHR];
+                for (int c = 0; c < CPR; ++c)
+                    old[l][c] = (EPI == EPI_ADDF) ? (TP)add[l * NF + threadIdx.x + c * NTHR]
+                                                  : out[l * NF + threadIdx.x + c * NTHR];
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
@@ -656,6 +660,7 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                     const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
                     const T val = (l & 1) ? sim[li(l >> 1, n, SP)] : sre[li(l >> 1, n, SP)];
                     if constexpr (EPI == EPI_ACC) out[e] += (TP)val;
+                    else if constexpr (EPI == EPI_ADDF) out[e] = (TP)a.add32[base + e] + (TP)val;
                     else out[e] = (TP)val;
                 }
             }

@@ -82,7 +82,7 @@ def test_plan_lifecycle_and_workspace_size_host_only():
     assert n * 8 <= sz.value < n * 8 + (64 << 20)          # FP64: one field + tables
     assert L.fsei_plan_set_precision(h, fsei.PREC_FP32_REFINE, 1e-10, 4) == OK
     assert L.fsei_plan_workspace_size(h, ctypes.byref(sz)) == OK
-    assert n * 20 <= sz.value < n * 20 + (64 << 20)        # f (8) + FP32 work (4) + p (8)
+    assert n * 24 <= sz.value < n * 24 + (64 << 20)        # f (8) + FP32 work (4) + p (8) + FP32 p (4)
     assert L.fsei_plan_set_precision(h, 7, 1e-10, 4) == ERR_ARG
     assert L.fsei_plan_set_precision(h, 0, -1.0, 4) == ERR_ARG
     assert L.fsei_plan_set_precision(h, 0, 1e-10, 65) == ERR_ARG

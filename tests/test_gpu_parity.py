@@ -289,3 +289,36 @@ def test_fp32_and_refine_fixed_length(dims, bc):
     assert info["rel_residual"] <= 1e-10
     assert oracle.rel_residual(oracle.divergence(u, v, w, g), gp, g) <= 1e-10
     assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
+
+
+def test_refine_without_corrections_returns_the_fp32_solve():
+    """max_iter = 0: the FP32 first solve, widened to FP64; its residual is
+    the one the library reports."""
+    F = fsei()
+    spec = W.small_spec(64, 48, 96, WALL, WALL, lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 12)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=0.0, max_iter=0)
+    f = oracle.divergence(u, v, w, g)
+    res = oracle.rel_residual(f, gp, g)
+    print("no-correction info", info, "host residual", res, "p err", rel(gp, rp))
+    assert info["iterations"] == 0
+    assert abs(info["rel_residual"] - res) <= 0.05 * res
+    assert rel(gp, rp) <= 1e-4 and max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 2e-5
+
+
+def test_refine_projection_two_corrections():
+    """rtol below what one correction reaches: the second correction adds to
+    the FP64 iterate written by the first."""
+    F = fsei()
+    spec = W.small_spec(512, 32, 12, WALL, WALL, lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 77)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-13, max_iter=4)
+    f = oracle.divergence(u, v, w, g)
+    print("two-correction info", info)
+    assert info["iterations"] == 2 and info["rel_residual"] <= 1e-13
+    assert oracle.rel_residual(f, gp, g) <= 1e-13
+    assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-11
