@@ -40,7 +40,8 @@ SLOT_KERNEL = {
                     "zsolve": "k_zsolve2<float, float, 32, 24, 1024>", "yinv": "k_yinv<float, 8192, 1024, 512>",
                     "xinv": "k_xinv<float, double, 0, 2048, 256, 512>", "xinv_acc": "k_xinv<float, double, 1, 2048, 256, 512>",
                     "resid": "k_resid_pairs<256, 8, true>", "resid_norm": "k_resid_pairs<256, 8, false>",
-                    "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256>"},
+                    "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256>",
+                    "grad_resid": "k_grad_resid<256, 8, false>"},
 }
 
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:
@@ -48,7 +49,7 @@ SLOT_KERNEL = {
 BYTES_PER_CELL = {
     "fp64": {"xfwd": 32, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "grad": 56},
     "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 12, "resid_xfwd": 20,
-                    "resid": 20, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 20, "grad": 56},
+                    "resid": 20, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 20, "grad": 56, "grad_resid": 64},
 }
 
 

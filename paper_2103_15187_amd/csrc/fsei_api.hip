@@ -21,11 +21,12 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "", ""};
+    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", ""};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
 constexpr int K_RESID_PAIRS = 12;
 constexpr int K_XFWD_R = 13;
+constexpr int K_GRAD_RESID = 14;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -167,9 +168,10 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
 }
 
 template <typename T, typename TP, int EPI>
-void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add32 = nullptr) {
+void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add32 = nullptr, T* keep = nullptr) {
     XInvArgs<T, TP> a{};
     a.add32 = add32;
+    a.keep = keep;
     a.nx = p->nx;
     a.ny = p->ny;
     a.nz = p->nz;
@@ -515,6 +517,48 @@ long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr, float* out
     return nb;
 }
 
+// Gradient correction of (u, v, w) fused with the residual norm partials of
+// the iterate p64 (DELTA: the gradient of the correction c32 instead of p64);
+// returns the number of partials written
+template <bool DELTA>
+long launch_grad_resid(fsei_plan* p, double* u, double* v, double* w, const double* f, const double* p64,
+                       const float* c32, double dt) {
+    GradResArgs a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.bcy = p->bcy;
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.p = p64;
+    a.c = c32;
+    a.cx = -dt / p->dx;
+    a.cy = -dt / p->dy;
+    a.sw = -dt;
+    a.bk = tab<double>(p, T_INV_H);
+    a.gk = tab<double>(p, T_INV_H);
+    a.f = f;
+    a.idx2 = 1.0 / (p->dx * p->dx);
+    a.idy2 = 1.0 / (p->dy * p->dy);
+    a.za = tab<double>(p, T_ZA);
+    a.zc = tab<double>(p, T_ZC);
+    a.scal = scalars(p);
+    a.partials = partials(p);
+    const long nb = (long)(p->ny / kPairRows) * p->nz;
+    const dim3 grid((unsigned)nb);
+    const int np = p->nx / 2;
+    Timed t(p, K_GRAD_RESID);
+    if (np >= 256)
+        hipLaunchKernelGGL((k_grad_resid<256, kPairRows, DELTA>), grid, dim3(256), 0, S(p), a);
+    else if (np > 64)
+        hipLaunchKernelGGL((k_grad_resid<128, kPairRows, DELTA>), grid, dim3(128), 0, S(p), a);
+    else
+        hipLaunchKernelGGL((k_grad_resid<64, kPairRows, DELTA>), grid, dim3(64), 0, S(p), a);
+    return nb;
+}
+
 template <typename TI, typename TO>
 XFwdArgs<TI, TO> div_args(const fsei_plan* p, const TI* u, const TI* v, const TI* w, const TI* gp, bool adjoint,
                           double dt) {
@@ -575,8 +619,22 @@ void reduce_partials(fsei_plan* p, int off, bool vmean = false, long nblk = -1) 
 //   p0 = solve32(f); repeat: r = (f - mean) - L p (FP64 stencil), stop when
 //   ||r|| <= rtol ||f - mean||, else p += solve32(r).
 // ---------------------------------------------------------------------------
+// Projection target of a refined solve: with the pair tiling and rtol > 0 the
+// gradient correction is fused with the convergence check of each
+// correction (the first applies the gradient of p, later ones the gradient of
+// their own correction); `applied` tells the caller whether it still has to
+// apply the gradient of the final p.
+struct RefineGrad {
+    double* u;
+    double* v;
+    double* w;
+    double dt;
+    bool applied;
+};
+
 template <int PRO>
-fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p64, fsei_info* info) {
+fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p64, fsei_info* info,
+                         RefineGrad* g = nullptr) {
     float* w32 = static_cast<float*>(field2(p));
     double* f64 = static_cast<double*>(field1(p));
     first.out = w32;
@@ -675,6 +733,8 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         fsei_status st = residual_norm();
         if (st != FSEI_OK) return st;
     }
+    const bool fuse = g != nullptr && pairs && p->rtol > 0.0 && aligned16(g->u) && aligned16(g->v) &&
+                      aligned16(g->w);
     while (!converged && it < p->max_iter) {
         launch_y<float>(p, w32, false);
         launch_z<float>(p, w32, 0, false);
@@ -682,14 +742,24 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         if (p_in_32) {
             launch_xinv<float, double, EPI_ADDF>(p, w32, p64, K_XINV_ACC, p32);   // p64 = p32 + delta
             p_in_32 = false;
+        } else if (fuse && g->applied) {
+            // p64 += delta, and delta itself kept (in w32) for its gradient
+            launch_xinv<float, double, EPI_ACC_KEEP>(p, w32, p64, K_XINV_ACC, nullptr, w32);
         } else {
             launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC);
         }
         ++it;
         measured = false;
         if (p->rtol > 0.0) {
-            // convergence check of the corrected iterate: norm only, no transform
-            norm_pass();
+            // convergence check of the corrected iterate: norm only, no
+            // transform; for a projection fused with the gradient correction
+            if (fuse) {
+                nres = g->applied ? launch_grad_resid<true>(p, g->u, g->v, g->w, f64, p64, w32, g->dt)
+                                  : launch_grad_resid<false>(p, g->u, g->v, g->w, f64, p64, nullptr, g->dt);
+                g->applied = true;
+            } else {
+                norm_pass();
+            }
             fsei_status st = residual_norm();
             if (st != FSEI_OK) return st;
             if (converged || floor) break;
@@ -811,9 +881,10 @@ fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* 
     if (p->precision == FSEI_PREC_FP32_REFINE) {
         double* p64 = pout ? pout : static_cast<double*>(field3(p));
         XFwdArgs<double, float> a = div_args<double, float>(p, u, v, w, nullptr, false, dt);
-        st = refine_solve<PRO_DIV>(p, a, p64, info);
+        RefineGrad g{u, v, w, dt, false};
+        st = refine_solve<PRO_DIV>(p, a, p64, info, &g);
         if (st != FSEI_OK && st != FSEI_ERR_NOT_CONVERGED) return st;
-        launch_grad<double, double>(p, u, v, w, p64, false, dt);
+        if (!g.applied) launch_grad<double, double>(p, u, v, w, p64, false, dt);
         fsei_status st2 = check_hip();
         return (st2 != FSEI_OK) ? st2 : st;
     }

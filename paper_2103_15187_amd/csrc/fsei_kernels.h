@@ -848,6 +848,145 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Gradient correction fused with the FP64 residual norm of the refinement's
+// current pressure iterate: u += cx (g_i - g_{i-1}), v += cy (g_j - g_{j-1}),
+// w += sw (bk_k g_k - gk_k g_{k-1}) with g = p (or, DELTA, with g = the last
+// correction c, applied on top of an earlier update), and the partials
+// (sum r^2, sum r, 0) of r = (f - mean) - L p.  Pair tiling as
+// k_resid_pairs.  The convergence check of the last correction then costs no
+// pass of its own.
+// ---------------------------------------------------------------------------
+struct GradResArgs {
+    int nx, ny, nz, bcx, bcy;
+    double* u;
+    double* v;
+    double* w;
+    const double* p;      // current iterate (residual; gradient unless DELTA)
+    const float* c;       // DELTA: the correction whose gradient is applied
+    double cx, cy, sw;
+    const double* bk;
+    const double* gk;
+    const double* f;
+    double idx2, idy2;
+    const double* za;
+    const double* zc;
+    const double* scal;   // scal[0] = removed mean
+    double* partials;
+};
+
+template <int NT, int RJ, bool DELTA>
+__global__ __launch_bounds__(NT) void k_grad_resid(GradResArgs a) {
+    constexpr int RB = 2;   // rows per load batch (20 doubles per row in flight)
+    static_assert(RJ % RB == 0, "whole batches");
+    __shared__ double sred[3 * (NT / 64)];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int jt = b / nz;
+    const int k = b - jt * nz;
+    const int j0 = jt * RJ;
+    const size_t nxy = (size_t)nx * ny;
+    const size_t pl = (size_t)k * nxy;
+    const double* __restrict__ pk = a.p + pl;
+    const double* __restrict__ pkm = (k > 0) ? pk - nxy : pk;
+    const double* __restrict__ pkp = (k + 1 < nz) ? pk + nxy : pk;
+    const float* __restrict__ ck = DELTA ? a.c + pl : nullptr;
+    const float* __restrict__ ckm = (DELTA && k > 0) ? ck - nxy : ck;
+    const double* __restrict__ fk = a.f + pl;
+    double* __restrict__ uk = a.u + pl;
+    double* __restrict__ vk = a.v + pl;
+    double* __restrict__ wk = a.w + pl;
+    const double czm = (k > 0) ? a.za[k] : 0.0, czp = (k + 1 < nz) ? a.zc[k] : 0.0;
+    const bool hzm = k > 0, hzp = k + 1 < nz;
+    const bool pery = a.bcy == FSEI_BC_PERIODIC, perx = a.bcx == FSEI_BC_PERIODIC;
+    const bool wallx = !perx, wally = !pery;
+    const double mean = a.scal[0];
+    const double bkk = a.bk[k], gkk = a.gk[k];
+    double ss = 0.0, s1 = 0.0;
+    for (int c = threadIdx.x; 2 * c < nx; c += NT) {
+        const unsigned i = 2u * (unsigned)c;
+        const unsigned im = (i > 0) ? i - 1 : (unsigned)nx - 1;
+        const unsigned ip = (i + 2 < (unsigned)nx) ? i + 2 : 0u;
+        const bool him = (i > 0) || perx, hip = (i + 2 < (unsigned)nx) || perx;
+        const int jm0 = (j0 > 0) ? j0 - 1 : ny - 1;
+        double2 pm = ld2d(pk + (size_t)jm0 * nx + i);
+        double2 pc = ld2d(pk + (size_t)j0 * nx + i);
+        double2 cm = make_double2(0.0, 0.0);
+        if constexpr (DELTA) cm = ld2d(ck + (size_t)jm0 * nx + i);
+#pragma unroll
+        for (int l0 = 0; l0 < RJ; l0 += RB) {
+            double2 pn[RB], pzm[RB], pzp[RB], fc[RB], uo[RB], vo[RB], wo[RB], cc[RB], czk[RB];
+            double pxm[RB], pxp[RB], cxm[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int j = j0 + l0 + r;
+                const size_t ro = (size_t)j * nx;
+                const int jn = (j + 1 < ny) ? j + 1 : 0;
+                pn[r] = ld2d(pk + (size_t)jn * nx + i);
+                pxm[r] = pk[ro + im];
+                pxp[r] = pk[ro + ip];
+                pzm[r] = ld2d(pkm + ro + i);
+                pzp[r] = ld2d(pkp + ro + i);
+                fc[r] = ld2d(fk + ro + i);
+                uo[r] = ld2d(uk + ro + i);
+                vo[r] = ld2d(vk + ro + i);
+                wo[r] = ld2d(wk + ro + i);
+                if constexpr (DELTA) {
+                    cc[r] = ld2d(ck + ro + i);
+                    cxm[r] = (double)ck[ro + im];
+                    czk[r] = ld2d(ckm + ro + i);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const int j = j0 + l0 + r;
+                const size_t ro = (size_t)j * nx;
+                const bool hym = (j > 0) || pery, hyp = (j + 1 < ny) || pery;
+                // residual of the current iterate (as k_resid_pairs)
+                const double lx0 = (pc.y - pc.x) + (him ? pxm[r] - pc.x : 0.0);
+                const double lx1 = (hip ? pxp[r] - pc.y : 0.0) + (pc.x - pc.y);
+                const double ly0 = (hyp ? pn[r].x - pc.x : 0.0) + (hym ? pm.x - pc.x : 0.0);
+                const double ly1 = (hyp ? pn[r].y - pc.y : 0.0) + (hym ? pm.y - pc.y : 0.0);
+                const double lz0 = (hzp ? czp * (pzp[r].x - pc.x) : 0.0) + (hzm ? czm * (pzm[r].x - pc.x) : 0.0);
+                const double lz1 = (hzp ? czp * (pzp[r].y - pc.y) : 0.0) + (hzm ? czm * (pzm[r].y - pc.y) : 0.0);
+                const double r0 = (fc[r].x - mean) - (lx0 * a.idx2 + ly0 * a.idy2 + lz0);
+                const double r1 = (fc[r].y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1);
+                ss += r0 * r0 + r1 * r1;
+                s1 += r0 + r1;
+                // gradient of g = p, or of the correction c
+                const double2 gc = DELTA ? cc[r] : pc;
+                const double2 gm = DELTA ? cm : pm;
+                const double gxm = DELTA ? cxm[r] : pxm[r];
+                const double2 gz = DELTA ? czk[r] : pzm[r];
+                double2 un, vn, wn;
+                un.x = (wallx && i == 0) ? 0.0 : uo[r].x + a.cx * (gc.x - gxm);
+                un.y = uo[r].y + a.cx * (gc.y - gc.x);
+                const bool v0 = wally && j == 0;
+                vn.x = v0 ? 0.0 : vo[r].x + a.cy * (gc.x - gm.x);
+                vn.y = v0 ? 0.0 : vo[r].y + a.cy * (gc.y - gm.y);
+                wn.x = (k == 0) ? 0.0 : wo[r].x + a.sw * (bkk * gc.x - gkk * gz.x);
+                wn.y = (k == 0) ? 0.0 : wo[r].y + a.sw * (bkk * gc.y - gkk * gz.y);
+                *reinterpret_cast<double2*>(uk + ro + i) = un;
+                *reinterpret_cast<double2*>(vk + ro + i) = vn;
+                *reinterpret_cast<double2*>(wk + ro + i) = wn;
+                pm = pc;
+                pc = pn[r];
+                if constexpr (DELTA) cm = cc[r];
+            }
+            // keep the next batch's loads after this batch's stores (bounds
+            // the registers to one batch)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    double s2 = 0.0;
+    block_sum3<NT>(ss, s1, s2, sred);
+    if (threadIdx.x == 0) {
+        a.partials[3 * blockIdx.x] = ss;
+        a.partials[3 * blockIdx.x + 1] = s1;
+        a.partials[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
 // out = (double) in, n values (grid-stride)
 __global__ __launch_bounds__(256) void k_widen(const float* __restrict__ in, double* __restrict__ out, size_t n) {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)

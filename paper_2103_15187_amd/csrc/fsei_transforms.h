@@ -534,7 +534,9 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
 // x inverse: unnormalised inverse x transform of row pairs; writes (STORE)
 // or adds (ACC) the result into the output field
 // ---------------------------------------------------------------------------
-enum { EPI_STORE = 0, EPI_ACC = 1, EPI_ADDF = 2 };   // ADDF: out = add32 + result
+// STORE: out = result; ACC: out += result; ADDF: out = add32 + result;
+// ACC_KEEP: out += result and the result is also written back over the input
+enum { EPI_STORE = 0, EPI_ACC = 1, EPI_ADDF = 2, EPI_ACC_KEEP = 3 };
 
 template <typename T, typename TP>
 struct XInvArgs {
@@ -543,6 +545,7 @@ struct XInvArgs {
     const T* in;
     TP* out;
     const float* add32;   // EPI_ADDF: FP32 field added to the result
+    T* keep;              // EPI_ACC_KEEP: receives the result (the input field itself)
     const T* twc;
     const T* tws;
     const T* dctc;
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
     const long row0 = xcd_remap(blockIdx.x, gridDim.x) * nl;
     const long nrows = (long)a.ny * a.nz;
     const size_t base = (size_t)row0 * N;
-    const T* __restrict__ in = a.in + base;
+    const T* in = a.in + base;   // not restrict: ACC_KEEP writes this field back (after every read of it)
     T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
     if constexpr (NF > 0) {
         static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
             const int i = threadIdx.x + c * NTHR;
             ln[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
         }
-        if constexpr (EPI == EPI_ACC || EPI == EPI_ADDF) {
+        if constexpr (EPI == EPI_ACC || EPI == EPI_ADDF || EPI == EPI_ACC_KEEP) {
             TP old[NL][CPR];
             const float* __restrict__ add = (EPI == EPI_ADDF) ? a.add32 + base : nullptr;
 #pragma unroll
@@ -638,6 +641,7 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                 for (int c = 0; c < CPR; ++c) {
                     const T val = (l & 1) ? sim[(l >> 1) * SP + ln[c]] : sre[(l >> 1) * SP + ln[c]];
                     out[l * NF + threadIdx.x + c * NTHR] = old[l][c] + (TP)val;
+                    if constexpr (EPI == EPI_ACC_KEEP) a.keep[base + l * NF + threadIdx.x + c * NTHR] = val;
                 }
         } else {
 #pragma unroll
@@ -661,7 +665,10 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                     const T val = (l & 1) ? sim[li(l >> 1, n, SP)] : sre[li(l >> 1, n, SP)];
                     if constexpr (EPI == EPI_ACC) out[e] += (TP)val;
                     else if constexpr (EPI == EPI_ADDF) out[e] = (TP)a.add32[base + e] + (TP)val;
-                    else out[e] = (TP)val;
+                    else if constexpr (EPI == EPI_ACC_KEEP) {
+                        out[e] += (TP)val;
+                        a.keep[base + e] = val;
+                    } else out[e] = (TP)val;
                 }
             }
         }
