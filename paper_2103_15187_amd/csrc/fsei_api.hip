@@ -685,11 +685,25 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     bool floor = false;      // a correction no longer halved the residual
     bool measured = false;   // rel belongs to the current iterate
     long nres = -1;   // partials of the last residual pass (-1: the xfwd tiles)
+    // The first solve's residual norm is reduced into scalars[8..10] but not
+    // read back on its own: it is fetched with the first corrected iterate's
+    // norm, so the common one-correction case waits on the host once.  (A
+    // first solve that already meets rtol then still gets one correction.)
+    bool first_pending = false;
+    double vmean = 0.0;
     auto residual_norm = [&]() -> fsei_status {
         reduce_partials(p, 1, false, nres);   // scalars[1..3]: sum r^2, sum r, 0
-        double h[8];
-        fsei_status st = read_scalars(p, h, 8);
+        double h[11];
+        fsei_status st = read_scalars(p, h, first_pending ? 11 : 8);
         if (st != FSEI_OK) return st;
+        vmean = h[0];
+        if (first_pending) {
+            double h0[8];
+            std::copy(h, h + 8, h0);
+            h0[1] = h[8];
+            rel = rel_from(h0);
+            first_pending = false;
+        }
         rel_prev = rel;
         rel = rel_from(h);
         measured = true;
@@ -730,8 +744,13 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     };
     resid_pass();
     if (p->rtol > 0.0) {
-        fsei_status st = residual_norm();
-        if (st != FSEI_OK) return st;
+        if (p->max_iter > 0) {
+            reduce_partials(p, 8, false, nres);
+            first_pending = true;
+        } else {
+            fsei_status st = residual_norm();
+            if (st != FSEI_OK) return st;
+        }
     }
     const bool fuse = g != nullptr && pairs && p->rtol > 0.0 && aligned16(g->u) && aligned16(g->v) &&
                       aligned16(g->w);
@@ -781,12 +800,15 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         if (st != FSEI_OK) return st;
     }
     if (info) {
-        double h[1];
-        fsei_status st = read_scalars(p, h, 1);
-        if (st != FSEI_OK) return st;
+        if (!measured) {
+            double h[1];
+            fsei_status st = read_scalars(p, h, 1);
+            if (st != FSEI_OK) return st;
+            vmean = h[0];
+        }
         info->iterations = it;
         info->rel_residual = rel;
-        info->rhs_vmean_removed = h[0];
+        info->rhs_vmean_removed = vmean;
         info->floor_reached = floor ? 1 : 0;
     }
     fsei_status st = check_hip();
