@@ -201,7 +201,9 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     const size_t dyn = 2 * p->ny * sizeof(T);
     // fixed-length variant: full tiles of the compile-time width, column
     // pairs addressed as one aligned vector
-    constexpr bool kFix = y_fixed_ok(EMAX, NTHR, 512);
+    constexpr int kPsF = yfwd_pad<T>();
+    constexpr bool kFix = y_fixed_ok(EMAX, NTHR, 512) && y_fixed_ok(EMAX, NTHR, 512, kPsF) &&
+                          tile_nseq(EMAX, 512, kPsF) == tile_nseq(EMAX, 512);
     const bool fix = kFix && p->ny == 512 && a.nseq == tile_nseq(EMAX, 512) && p->nx % tx == 0 &&
                      reinterpret_cast<uintptr_t>(a.data) % (2 * sizeof(T)) == 0;
     if (inverse) {
@@ -217,7 +219,7 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
         Timed t(p, K_YFWD);
         if constexpr (kFix) {
             if (fix) {
-                hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+                hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512, kPsF>), dim3(nb), dim3(NTHR), dyn, S(p), a);
                 return;
             }
         }

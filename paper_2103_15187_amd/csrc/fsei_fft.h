@@ -24,7 +24,8 @@ namespace fsei {
 namespace dev {
 
 // seq_stride, lds_elems and tile_nseq (the tile geometry) live in fsei_plan.h
-__device__ __forceinline__ int li(int s, int n, int SP) { return s * SP + n + (n >> 4); }
+template <int PS = kPadShift>
+__device__ __forceinline__ int li(int s, int n, int SP) { return s * SP + n + (n >> PS); }
 
 template <typename T>
 __device__ __forceinline__ void cmul(T& ar, T& ai, T br, T bi) {
@@ -122,7 +123,7 @@ __device__ __forceinline__ void dftR(T* xr, T* xi) {
 // One Stockham stage of radix R over all nseq sequences.  MAXB bounds the
 // butterflies per thread: nseq*N/R <= MAXB*blockDim.x.  N and Ns are
 // compile-time constants when the caller's are.
-template <typename T, int R, int MAXB, int SIGN, int NTHR>
+template <typename T, int R, int MAXB, int SIGN, int NTHR, int PS = kPadShift>
 __device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im, int N, int SP, int nseq, int Ns,
                                           const T* __restrict__ twc, const T* __restrict__ tws) {
     const int NR = N / R;
@@ -140,7 +141,7 @@ __device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im
             const int k = j % Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int o = li(s, j + r * NR, SP);
+                const int o = li<PS>(s, j + r * NR, SP);
                 vr[b][r] = re[o];
                 vi[b][r] = im[o];
             }
@@ -163,7 +164,7 @@ __device__ __forceinline__ void fft_stage(T* __restrict__ re, T* __restrict__ im
             const int pos = dst[b] & ((1 << 20) - 1);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int o = li(s, pos + r * Ns, SP);
+                const int o = li<PS>(s, pos + r * Ns, SP);
                 re[o] = vr[b][r];
                 im[o] = vi[b][r];
             }
@@ -201,35 +202,35 @@ __host__ __device__ constexpr int stage_radix(int n, int st) {
     return 3;
 }
 
-template <typename T, int EMAX, int NTHR, int SIGN, int NF, int ST, int NS>
+template <typename T, int EMAX, int NTHR, int SIGN, int NF, int ST, int NS, int PS = kPadShift>
 __device__ __forceinline__ void fft_fixed(T* re, T* im, int nseq, const T* __restrict__ twc,
                                           const T* __restrict__ tws) {
     if constexpr (ST < num_stages(NF)) {
         constexpr int R = stage_radix(NF, ST);
-        fft_stage<T, R, cdiv(EMAX, NTHR * R), SIGN, NTHR>(re, im, NF, seq_stride(NF), nseq, NS, twc, tws);
-        fft_fixed<T, EMAX, NTHR, SIGN, NF, ST + 1, NS * R>(re, im, nseq, twc, tws);
+        fft_stage<T, R, cdiv(EMAX, NTHR * R), SIGN, NTHR, PS>(re, im, NF, seq_stride(NF, PS), nseq, NS, twc, tws);
+        fft_fixed<T, EMAX, NTHR, SIGN, NF, ST + 1, NS * R, PS>(re, im, nseq, twc, tws);
     }
 }
 
 // Full transform of nseq sequences (nseq*N <= EMAX) with NTHR threads.
-template <typename T, int EMAX, int NTHR, int SIGN, int NF>
+template <typename T, int EMAX, int NTHR, int SIGN, int NF, int PS = kPadShift>
 __device__ __forceinline__ void fft_lds(T* re, T* im, int N, int nseq, const FftPlan& pl,
                                         const T* __restrict__ twc, const T* __restrict__ tws) {
     if constexpr (NF > 0) {
-        fft_fixed<T, EMAX, NTHR, SIGN, NF, 0, 1>(re, im, nseq, twc, tws);
+        fft_fixed<T, EMAX, NTHR, SIGN, NF, 0, 1, PS>(re, im, nseq, twc, tws);
     } else {
-        const int SP = seq_stride(N);
+        const int SP = seq_stride(N, PS);
         int Ns = 1;
         for (int st = 0; st < pl.nstages; ++st) {
             const int R = pl.radix[st];
             if (R == 8)
-                fft_stage<T, 8, cdiv(EMAX, NTHR * 8), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+                fft_stage<T, 8, cdiv(EMAX, NTHR * 8), SIGN, NTHR, PS>(re, im, N, SP, nseq, Ns, twc, tws);
             else if (R == 4)
-                fft_stage<T, 4, cdiv(EMAX, NTHR * 4), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+                fft_stage<T, 4, cdiv(EMAX, NTHR * 4), SIGN, NTHR, PS>(re, im, N, SP, nseq, Ns, twc, tws);
             else if (R == 2)
-                fft_stage<T, 2, cdiv(EMAX, NTHR * 2), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+                fft_stage<T, 2, cdiv(EMAX, NTHR * 2), SIGN, NTHR, PS>(re, im, N, SP, nseq, Ns, twc, tws);
             else
-                fft_stage<T, 3, cdiv(EMAX, NTHR * 3), SIGN, NTHR>(re, im, N, SP, nseq, Ns, twc, tws);
+                fft_stage<T, 3, cdiv(EMAX, NTHR * 3), SIGN, NTHR, PS>(re, im, N, SP, nseq, Ns, twc, tws);
             Ns *= R;
         }
     }

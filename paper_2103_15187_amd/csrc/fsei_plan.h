@@ -23,10 +23,13 @@ inline int x_emax(int) { return 2048; }
 // LDS tile geometry shared by the host (launch sizes) and the kernels:
 // sequence s of length N starts at s * seq_stride(N); one array of a tile of
 // emax complex elements holds lds_elems(emax) slots.
-constexpr int seq_stride(int N) { return N + (N >> 4) + 1; }
-constexpr int lds_elems(int emax) { return emax + (emax >> 4) + 16; }
-constexpr int tile_nseq(int emax, int N) {
-    return (emax / N < lds_elems(emax) / seq_stride(N)) ? emax / N : lds_elems(emax) / seq_stride(N);
+// One pad slot every 2^ps elements (ps = kPadShift unless a kernel picks its
+// own: the best pad depends on the kernel's access pattern and is measured).
+constexpr int kPadShift = 4;
+constexpr int seq_stride(int N, int ps = kPadShift) { return N + (N >> ps) + 1; }
+constexpr int lds_elems(int emax, int ps = kPadShift) { return emax + (emax >> ps) + 16; }
+constexpr int tile_nseq(int emax, int N, int ps = kPadShift) {
+    return (emax / N < lds_elems(emax, ps) / seq_stride(N, ps)) ? emax / N : lds_elems(emax, ps) / seq_stride(N, ps);
 }
 inline int x_nseq(int nx) { return tile_nseq(x_emax(nx), nx) > 0 ? tile_nseq(x_emax(nx), nx) : 1; }
 

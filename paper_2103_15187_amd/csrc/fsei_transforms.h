@@ -84,15 +84,15 @@ __device__ __forceinline__ T* lds_twiddles(const T* __restrict__ twc, const T* _
 }
 
 // forward post-processing of pair s: the two real outputs at row m
-template <typename T>
+template <typename T, int PS = kPadShift>
 __device__ __forceinline__ void post_fwd(const T* re, const T* im, int s, int SP, int N, int m, int bc,
                                          const T* __restrict__ dctc, const T* __restrict__ dcts, T& xa,
                                          T& xb) {
     const T half = (T)0.5;
     if (bc == FSEI_BC_WALL) {
         const int mm = (m == 0) ? 0 : N - m;
-        const T zr = re[li(s, m, SP)], zi = im[li(s, m, SP)];
-        const T cr = re[li(s, mm, SP)], ci = im[li(s, mm, SP)];
+        const T zr = re[li<PS>(s, m, SP)], zi = im[li<PS>(s, m, SP)];
+        const T cr = re[li<PS>(s, mm, SP)], ci = im[li<PS>(s, mm, SP)];
         const T ar = (zr + cr) * half, ai = (zi - ci) * half;
         const T br = (zi + ci) * half, bi = (cr - zr) * half;
         const T wr = dctc[m], wi = -dcts[m];
@@ -101,12 +101,12 @@ __device__ __forceinline__ void post_fwd(const T* re, const T* im, int s, int SP
     } else {
         if (2 * m <= N) {
             const int mm = (m == 0) ? 0 : N - m;
-            xa = (re[li(s, m, SP)] + re[li(s, mm, SP)]) * half;
-            xb = (im[li(s, m, SP)] + im[li(s, mm, SP)]) * half;
+            xa = (re[li<PS>(s, m, SP)] + re[li<PS>(s, mm, SP)]) * half;
+            xb = (im[li<PS>(s, m, SP)] + im[li<PS>(s, mm, SP)]) * half;
         } else {
             const int q = N - m;
-            xa = (im[li(s, q, SP)] - im[li(s, m, SP)]) * half;
-            xb = (re[li(s, m, SP)] - re[li(s, q, SP)]) * half;
+            xa = (im[li<PS>(s, q, SP)] - im[li<PS>(s, m, SP)]) * half;
+            xb = (re[li<PS>(s, m, SP)] - re[li<PS>(s, q, SP)]) * half;
         }
     }
 }
@@ -221,10 +221,15 @@ __device__ __forceinline__ void post_fwd_v(int bc, bool lo, T zr, T zi, T cr, T 
 
 // whether the fixed y tile of EMAX elements and NTHR threads at length NF
 // gives every thread whole column pairs on an even number of rows per pass
-__host__ __device__ constexpr bool y_fixed_ok(int emax, int nthr, int nf) {
-    return tile_nseq(emax, nf) > 0 && nthr % tile_nseq(emax, nf) == 0 && nf % (nthr / tile_nseq(emax, nf)) == 0 &&
-           (nthr / tile_nseq(emax, nf)) % 2 == 0;
+__host__ __device__ constexpr bool y_fixed_ok(int emax, int nthr, int nf, int ps = kPadShift) {
+    return tile_nseq(emax, nf, ps) > 0 && nthr % tile_nseq(emax, nf, ps) == 0 &&
+           nf % (nthr / tile_nseq(emax, nf, ps)) == 0 && (nthr / tile_nseq(emax, nf, ps)) % 2 == 0;
 }
+
+// LDS pad of the fixed-length y forward kernel: FP32 tiles run fastest with
+// one pad slot per 64 elements, FP64 tiles with one per 16 (measured)
+template <typename T>
+constexpr int yfwd_pad() { return sizeof(T) == 4 ? 6 : kPadShift; }
 
 // two adjacent values of a field as one vector access
 template <typename T>
@@ -690,13 +695,13 @@ struct YArgs {
     const T* dcts;
 };
 
-template <typename T, int EMAX, int NTHR, int NF>
+template <typename T, int EMAX, int NTHR, int NF, int PS = kPadShift>
 __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
-    __shared__ T sre[lds_elems(EMAX)];
-    __shared__ T sim[lds_elems(EMAX)];
-    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF) : 0;
+    __shared__ T sre[lds_elems(EMAX, PS)];
+    __shared__ T sim[lds_elems(EMAX, PS)];
+    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF, PS) : 0;
     const int N = NF > 0 ? NF : a.ny;
-    const int SP = seq_stride(N);
+    const int SP = seq_stride(N, PS);
     const int nx = a.nx;
     const int nseq = NF > 0 ? NSF : a.nseq;
     const int TX = 2 * nseq;
@@ -718,7 +723,7 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < NPASS; ++r) {
             const int j = jr + r * RPP;
-            const int o = s * SP + li(0, (a.bcy == FSEI_BC_WALL) ? mk_pos(j, NF) : j, SP);
+            const int o = s * SP + li<PS>(0, (a.bcy == FSEI_BC_WALL) ? mk_pos(j, NF) : j, SP);
             sre[o] = val[r].x;
             sim[o] = val[r].y;
         }
@@ -739,13 +744,13 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
                 const int j = e / TX;
                 const int c = e - j * TX;
                 const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
-                if (c & 1) sim[li(c >> 1, n, SP)] = val[r];
-                else sre[li(c >> 1, n, SP)] = val[r];
+                if (c & 1) sim[li<PS>(c >> 1, n, SP)] = val[r];
+                else sre[li<PS>(c >> 1, n, SP)] = val[r];
             }
         }
     }
     __syncthreads();
-    fft_lds<T, EMAX, NTHR, -1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
+    fft_lds<T, EMAX, NTHR, -1, NF, PS>(sre, sim, N, nseq, a.fp, twl, twl + N);
     if constexpr (NF > 0) {
         using V2 = typename Vec2T<T>::type;
         constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
@@ -755,7 +760,7 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
         for (int r = 0; r < NPASS; ++r) {
             const int m = mr + r * RPP;
             const int mm = (m == 0) ? 0 : NF - m;
-            const int om = s * SP + li(0, m, SP), omm = s * SP + li(0, mm, SP);
+            const int om = s * SP + li<PS>(0, m, SP), omm = s * SP + li<PS>(0, mm, SP);
             T wr = (T)1, wi = (T)0;
             if (a.bcy == FSEI_BC_WALL) {
                 wr = a.dctc[m];
@@ -774,7 +779,7 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
                 const int m = e / nseq;
                 const int s = e - m * nseq;
                 T xa, xb;
-                post_fwd<T>(sre, sim, s, SP, N, m, a.bcy, a.dctc, a.dcts, xa, xb);
+                post_fwd<T, PS>(sre, sim, s, SP, N, m, a.bcy, a.dctc, a.dcts, xa, xb);
                 if (i0 + 2 * s < nx) d[m * nx + 2 * s] = xa;
                 if (i0 + 2 * s + 1 < nx) d[m * nx + 2 * s + 1] = xb;
             }
