@@ -258,8 +258,10 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
         launch_y_cfg<T, (sizeof(T) == 8 ? 8192 : 16384), 1024>(p, a, inverse);
 }
 
-// Tiling of the z solve: 0 = two adjacent modes per lane, 32 (FP64) / 64
-// (FP32) modes per workgroup, at most 32 chunks per line (needs nx even);
+// Tiling of the z solve: 0 = adjacent modes per lane as one vector: two
+// (FP64, 32 modes per workgroup) or four (FP32, 64 modes per workgroup; two
+// per lane in 1024-thread workgroups when nx % 4 != 0), at most 32 chunks per
+// line (needs nx even); 4 = FP32 with two modes per lane only;
 // 1 = 8 (FP64) / 16 (FP32) modes, one per lane, up to 64 chunks; 2 (FP64) =
 // 16 modes, one per lane, up to 64 chunks in 1024-thread workgroups; 3 = two
 // modes per lane, 16 (FP64) / 32 (FP32) modes, up to 64 chunks.  All tilings do the same work; the
@@ -301,16 +303,16 @@ void z_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid, int slot) {
     }
 }
 
-template <typename TS, typename TC, int TXL2, int NT>
-void z2_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid) {
+template <typename TS, typename TC, int M, int TXLM, int NT>
+void zv_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid) {
     Timed t(p, K_ZSOLVE);
     switch (a.L) {
-        case 4: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 4, NT>), grid, dim3(NT), 0, S(p), a); break;
-        case 8: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 8, NT>), grid, dim3(NT), 0, S(p), a); break;
-        case 12: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 12, NT>), grid, dim3(NT), 0, S(p), a); break;
-        case 16: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 16, NT>), grid, dim3(NT), 0, S(p), a); break;
-        case 24: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 24, NT>), grid, dim3(NT), 0, S(p), a); break;
-        default: hipLaunchKernelGGL((k_zsolve2<TS, TC, TXL2, 32, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 4: hipLaunchKernelGGL((k_zsolvev<TS, TC, M, TXLM, 4, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 8: hipLaunchKernelGGL((k_zsolvev<TS, TC, M, TXLM, 8, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 12: hipLaunchKernelGGL((k_zsolvev<TS, TC, M, TXLM, 12, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 16: hipLaunchKernelGGL((k_zsolvev<TS, TC, M, TXLM, 16, NT>), grid, dim3(NT), 0, S(p), a); break;
+        case 24: hipLaunchKernelGGL((k_zsolvev<TS, TC, M, TXLM, 24, NT>), grid, dim3(NT), 0, S(p), a); break;
+        default: hipLaunchKernelGGL((k_zsolvev<TS, TC, M, TXLM, 32, NT>), grid, dim3(NT), 0, S(p), a); break;
     }
 }
 
@@ -346,11 +348,11 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
-            z2_dispatch<double, double, 16, 512>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
+            zv_dispatch<double, double, 2, 16, 512>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
         } else if (cfg == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
-            z2_dispatch<double, double, 8, 512>(p, a, dim3((p->nx / 2 + 7) / 8, p->ny));
+            zv_dispatch<double, double, 2, 8, 512>(p, a, dim3((p->nx / 2 + 7) / 8, p->ny));
         } else if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
@@ -373,14 +375,18 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
         a.sigma_thr = (float)p->sigma_thr;
         int L, P;
-        if (zcfg() == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+        if (zcfg() == 0 && p->nx % 4 == 0 && choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
-            z2_dispatch<float, float, 32, 1024>(p, a, dim3((p->nx / 2 + 31) / 32, p->ny));
+            zv_dispatch<float, float, 4, 16, 512>(p, a, dim3((p->nx / 4 + 15) / 16, p->ny));
+        } else if ((zcfg() == 0 || zcfg() == 4) && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+            a.L = L;
+            a.P = P;
+            zv_dispatch<float, float, 2, 32, 1024>(p, a, dim3((p->nx / 2 + 31) / 32, p->ny));
         } else if (zcfg() == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
-            z2_dispatch<float, float, 16, 1024>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
+            zv_dispatch<float, float, 2, 16, 1024>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
         } else if (zcfg() == 1 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;

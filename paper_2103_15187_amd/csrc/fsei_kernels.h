@@ -244,21 +244,22 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Same solver with two adjacent modes (qx, qx+1) per lane: the global
-// accesses become 16-byte (FP64) / 8-byte (FP32) vectors and a workgroup
-// row segment covers 2*TXL2 modes (256 B), which streams markedly better
-// from HBM than 128-B segments; the two lines' recurrences also interleave.
-// Dense mode only; needs nx even.
+// Same solver with M adjacent modes (qx .. qx+M-1) per lane: the global
+// accesses become one M-wide vector (16 bytes for two FP64 or four FP32
+// modes) and a workgroup row segment covers M*TXLM modes (256 B), which
+// streams markedly better from HBM than 128-B segments; the M lines'
+// recurrences also interleave.  Dense mode only; needs nx % M == 0.
 // ---------------------------------------------------------------------------
-template <typename T> struct Vec2;
-template <> struct Vec2<double> { using type = double2; };
-template <> struct Vec2<float> { using type = float2; };
+template <typename T, int M> struct VecM;
+template <> struct VecM<double, 2> { using type = double2; };
+template <> struct VecM<float, 2> { using type = float2; };
+template <> struct VecM<float, 4> { using type = float4; };
 
-template <typename TS, typename TC, int TXL2, int L, int NT>
-__global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
-    using V = typename Vec2<TS>::type;
-    constexpr int PMAX = NT / TXL2;
-    __shared__ TC sh[4][2 * NT];
+template <typename TS, typename TC, int M, int TXLM, int L, int NT>
+__global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
+    using V = typename VecM<TS, M>::type;
+    constexpr int PMAX = NT / TXLM;
+    __shared__ TC sh[4][M * NT];
     __shared__ TC ta[PMAX * L], tc[PMAX * L], tb[PMAX * L], tm[PMAX * L], tsi[PMAX * L], tso[PMAX * L];
     const int nx = a.nx, nz = a.nz, P = a.P;
     const int npad = P * L;
@@ -271,15 +272,16 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
         tsi[k] = in ? (a.transposed ? a.scale * a.inv_dz[k] : a.scale) : (TC)0;
         tso[k] = in ? (a.transposed ? a.dz[k] : (TC)1) : (TC)0;
     }
-    const int ln = threadIdx.x % TXL2;
-    const int p = threadIdx.x / TXL2;
-    const int qx0 = (blockIdx.x * TXL2 + ln) * 2;
+    const int ln = threadIdx.x % TXLM;
+    const int p = threadIdx.x / TXLM;
+    const int qx0 = (blockIdx.x * TXLM + ln) * M;
     const int qy = blockIdx.y;
-    const size_t stride2 = (size_t)nx * a.ny / 2;   // in vectors
-    bool act[2];
-    TC sigma[2];
+    const size_t strideV = (size_t)nx * a.ny / M;   // in vectors
+    bool act[M];
+    TC sigma[M];
+    bool anyl = false, alll = true;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < M; ++h) {
         const int qx = qx0 + h;
         act[h] = qx < nx;
         sigma[h] = (TC)-1;
@@ -288,39 +290,48 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
             if ((qx == 0 && qy == 0) || fabs(sigma[h]) < a.sigma_thr) act[h] = false;
             if (!act[h]) sigma[h] = (TC)-1;
         }
+        anyl = anyl || act[h];
+        alll = alll && act[h];
     }
     const bool inrange = p < P;
     const int s0 = inrange ? p * L : 0;
-    const bool anyact = (act[0] || act[1]) && inrange;
+    const bool anyact = anyl && inrange;
     V* __restrict__ col = reinterpret_cast<V*>(a.data + (size_t)qy * nx + (qx0 < nx ? qx0 : 0));
 
-    TC F[2][L], Rr[2][L];
+    TC F[M][L], Rr[M][L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         const int k = s0 + t;
-        V v;
-        v.x = (TS)0;
-        v.y = (TS)0;
-        if (anyact && k < nz) v = col[(size_t)k * stride2];
-        F[0][t] = (TC)v.x;
-        F[1][t] = (TC)v.y;
+        V v{};
+        if (anyact && k < nz) v = col[(size_t)k * strideV];
+        const TS* e = reinterpret_cast<const TS*>(&v);
+#pragma unroll
+        for (int h = 0; h < M; ++h) F[h][t] = (TC)e[h];
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-        F[0][t] *= tsi[s0 + t];
-        F[1][t] *= tsi[s0 + t];
-    }
-    // downward sweep of both lines (interleaved), first-row back
+    for (int t = 0; t < L; ++t)
+#pragma unroll
+        for (int h = 0; h < M; ++h) F[h][t] *= tsi[s0 + t];
+    // downward sweep of the M lines (interleaved), first-row back
     // substitution accumulated as running sums (see k_zsolve)
-    TC cp[2] = {0, 0}, dp[2] = {0, 0}, g[2] = {1, 1}, pi[2] = {1, 1}, ys[2] = {0, 0}, gs[2] = {0, 0};
+    TC cp[M], dp[M], g[M], pi[M], ys[M], gs[M];
+#pragma unroll
+    for (int h = 0; h < M; ++h) {
+        cp[h] = 0;
+        dp[h] = 0;
+        g[h] = 1;
+        pi[h] = 1;
+        ys[h] = 0;
+        gs[h] = 0;
+    }
 #pragma unroll
     for (int t = 0; t < L - 1; ++t) {
         const int k = s0 + t;
-        const TC A = ta[k], C = tc[k], B0 = tb[k], M = tm[k];
+        const TC A = ta[k], C = tc[k], B0 = tb[k], Mk = tm[k];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const TC r = zrcp(B0 + sigma[h] * M - A * cp[h]);
+        for (int h = 0; h < M; ++h) {
+            const TC r = zrcp(B0 + sigma[h] * Mk - A * cp[h]);
             Rr[h][t] = r;
             dp[h] = (F[h][t] - A * dp[h]) * r;
             g[h] = -A * g[h] * r;
@@ -332,16 +343,16 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
         __builtin_amdgcn_sched_barrier(0);
     }
     const int me = threadIdx.x;
-    TC al[2], be[2], ga[2], ph[2];
+    TC al[M], be[M], ga[M], ph[M];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        sh[0][2 * me + h] = ys[h];    // Y_first
-        sh[1][2 * me + h] = gs[h];    // G_first
-        sh[2][2 * me + h] = pi[h];    // H_first
+    for (int h = 0; h < M; ++h) {
+        sh[0][M * me + h] = ys[h];    // Y_first
+        sh[1][M * me + h] = gs[h];    // G_first
+        sh[2][M * me + h] = pi[h];    // H_first
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < M; ++h) {
         al[h] = 0;
         be[h] = 1;
         ga[h] = 0;
@@ -353,37 +364,37 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
             be[h] = Be - Ae * cp[h];
             ph[h] = F[h][L - 1] - Ae * dp[h];
             if (p + 1 < P) {
-                const int nb = 2 * (me + TXL2) + h;
+                const int nb = M * (me + TXLM) + h;
                 be[h] += Ce * sh[1][nb];
                 ga[h] = Ce * sh[2][nb];
                 ph[h] -= Ce * sh[0][nb];
             }
         }
     }
-    // parallel cyclic reduction of the reduced systems of both lines
+    // parallel cyclic reduction of the reduced systems of the M lines
     for (int s = 1; s < P; s <<= 1) {
         __syncthreads();
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            sh[0][2 * me + h] = al[h];
-            sh[1][2 * me + h] = be[h];
-            sh[2][2 * me + h] = ga[h];
-            sh[3][2 * me + h] = ph[h];
+        for (int h = 0; h < M; ++h) {
+            sh[0][M * me + h] = al[h];
+            sh[1][M * me + h] = be[h];
+            sh[2][M * me + h] = ga[h];
+            sh[3][M * me + h] = ph[h];
         }
         __syncthreads();
         if (inrange) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < M; ++h) {
                 TC k1 = 0, k2 = 0, alm = 0, gam = 0, phm = 0, alp = 0, gap = 0, php = 0;
                 if (p - s >= 0) {
-                    const int id = 2 * (me - s * TXL2) + h;
+                    const int id = M * (me - s * TXLM) + h;
                     k1 = al[h] * zrcp(sh[1][id]);
                     alm = sh[0][id];
                     gam = sh[2][id];
                     phm = sh[3][id];
                 }
                 if (p + s < P) {
-                    const int id = 2 * (me + s * TXL2) + h;
+                    const int id = M * (me + s * TXLM) + h;
                     k2 = ga[h] * zrcp(sh[1][id]);
                     alp = sh[0][id];
                     gap = sh[2][id];
@@ -398,55 +409,54 @@ __global__ __launch_bounds__(NT) void k_zsolve2(ZArgs<TS, TC> a) {
     }
     __syncthreads();
 #pragma unroll
-    for (int h = 0; h < 2; ++h) sh[0][2 * me + h] = ph[h] * zrcp(be[h]);
+    for (int h = 0; h < M; ++h) sh[0][M * me + h] = ph[h] * zrcp(be[h]);
     __syncthreads();
-    TC XR[2], XL[2];
+    TC XR[M], prev[M];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        XR[h] = sh[0][2 * me + h];
-        XL[h] = (p > 0) ? sh[0][2 * (me - TXL2) + h] : (TC)0;
+    for (int h = 0; h < M; ++h) {
+        XR[h] = sh[0][M * me + h];
+        prev[h] = (p > 0) ? sh[0][M * (me - TXLM) + h] : (TC)0;   // x left of the chunk
     }
-    TC prev[2] = {XL[0], XL[1]};
 #pragma unroll
     for (int t = 0; t < L - 1; ++t) {
         const TC A = ta[s0 + t];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < M; ++h) {
             prev[h] = (F[h][t] - A * prev[h]) * Rr[h][t];
             F[h][t] = prev[h];
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    TC nxt[2] = {XR[0], XR[1]};
-    F[0][L - 1] = XR[0];
-    F[1][L - 1] = XR[1];
+#pragma unroll
+    for (int h = 0; h < M; ++h) F[h][L - 1] = XR[h];
 #pragma unroll
     for (int t = L - 2; t >= 0; --t) {
         const TC C = tc[s0 + t];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            nxt[h] = F[h][t] - C * Rr[h][t] * nxt[h];
-            F[h][t] = nxt[h];
+        for (int h = 0; h < M; ++h) {
+            XR[h] = F[h][t] - C * Rr[h][t] * XR[h];
+            F[h][t] = XR[h];
         }
         __builtin_amdgcn_sched_barrier(0);
     }
     if (anyact) {
-        V* out = col + (size_t)s0 * stride2;
+        V* out = col + (size_t)s0 * strideV;
         asm volatile("" : "+v"(out));
         TS* outs = reinterpret_cast<TS*>(out);
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             if (s0 + t < nz) {
                 const TC so = tso[s0 + t];
-                if (act[0] && act[1]) {
+                if (alll) {
                     V v;
-                    v.x = (TS)(F[0][t] * so);
-                    v.y = (TS)(F[1][t] * so);
-                    out[(size_t)t * stride2] = v;
-                } else if (act[0]) {
-                    outs[(size_t)t * 2 * stride2] = (TS)(F[0][t] * so);
+                    TS* e = reinterpret_cast<TS*>(&v);
+#pragma unroll
+                    for (int h = 0; h < M; ++h) e[h] = (TS)(F[h][t] * so);
+                    out[(size_t)t * strideV] = v;
                 } else {
-                    outs[(size_t)t * 2 * stride2 + 1] = (TS)(F[1][t] * so);
+#pragma unroll
+                    for (int h = 0; h < M; ++h)
+                        if (act[h]) outs[(size_t)t * M * strideV + h] = (TS)(F[h][t] * so);
                 }
             }
         }
