@@ -403,7 +403,10 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
     if constexpr (NF > 0) {
         static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
         constexpr int CPR = NF / NTHR, NL = 2 * NSF;
-        constexpr int RB = (NL % 4 == 0) ? 4 : ((NL % 2 == 0) ? 2 : 1);   // rows per load batch
+        // rows per load batch (the residual stencil loads 8 values per cell:
+        // two rows keep its registers within four waves per SIMD)
+        constexpr int RB0 = (PRO == PRO_RESID) ? 2 : 4;
+        constexpr int RB = (NL % RB0 == 0) ? RB0 : ((NL % 2 == 0) ? 2 : 1);
         ColNb cn[CPR];
         int lp[CPR];
 #pragma unroll
