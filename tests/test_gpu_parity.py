@@ -322,3 +322,20 @@ def test_refine_projection_two_corrections():
     assert info["iterations"] == 2 and info["rel_residual"] <= 1e-13
     assert oracle.rel_residual(f, gp, g) <= 1e-13
     assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-11
+
+
+@pytest.mark.parametrize("dims,bc", [((27, 18, 40), (WALL, PERIODIC)), ((64, 36, 50), (PERIODIC, WALL))])
+def test_refine_projection_generic_tiling(dims, bc):
+    """Shapes outside the pair tiling (odd nx, or ny not a multiple of 8): the
+    residual is the x-forward kernel's prologue and the FP64 iterate is
+    written by the first solve directly."""
+    F = fsei()
+    spec = W.small_spec(*dims, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 21)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6)
+    print("generic-tiling refine info", info)
+    assert info["rel_residual"] <= 1e-10
+    assert oracle.rel_residual(oracle.divergence(u, v, w, g), gp, g) <= 1e-10
+    assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
