@@ -353,6 +353,7 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
             a.L = L;
             a.P = P;
             zv_dispatch<double, double, 2, 8, 512>(p, a, dim3((p->nx / 2 + 7) / 8, p->ny));
+
         } else if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;

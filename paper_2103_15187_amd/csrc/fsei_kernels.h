@@ -150,7 +150,6 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
         gsum += g * pi;
         cp = C * r;
         pi *= -cp;
-        __builtin_amdgcn_sched_barrier(0);
     }
     const TC Ylast = dp, Glast = g, Hlast = -cp;
     const TC dh = ysum, ch = -gsum, hh = pi;
@@ -221,7 +220,6 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
     for (int t = 0; t < L - 1; ++t) {
         prev = (F[t] - ta[s0 + t] * prev) * Rr[t];
         F[t] = prev;
-        __builtin_amdgcn_sched_barrier(0);
     }
     F[L - 1] = XR;
     TC nxt = XR;
@@ -229,7 +227,6 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
     for (int t = L - 2; t >= 0; --t) {
         nxt = F[t] - tc[s0 + t] * Rr[t] * nxt;
         F[t] = nxt;
-        __builtin_amdgcn_sched_barrier(0);
     }
     if (ld) {
         // fresh base address (opaque to the compiler) so the per-row load
@@ -340,7 +337,6 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
             cp[h] = C * r;
             pi[h] *= -cp[h];
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
     const int me = threadIdx.x;
     TC al[M], be[M], ga[M], ph[M];
@@ -425,7 +421,6 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
             prev[h] = (F[h][t] - A * prev[h]) * Rr[h][t];
             F[h][t] = prev[h];
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int h = 0; h < M; ++h) F[h][L - 1] = XR[h];
@@ -437,7 +432,6 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
             XR[h] = F[h][t] - C * Rr[h][t] * XR[h];
             F[h][t] = XR[h];
         }
-        __builtin_amdgcn_sched_barrier(0);
     }
     if (anyact) {
         V* out = col + (size_t)s0 * strideV;
