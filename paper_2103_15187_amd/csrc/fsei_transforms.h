@@ -405,7 +405,7 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
         constexpr int CPR = NF / NTHR, NL = 2 * NSF;
         // rows per load batch (the residual stencil loads 8 values per cell:
         // two rows keep its registers within four waves per SIMD)
-        constexpr int RB0 = (PRO == PRO_RESID) ? 2 : 4;
+        constexpr int RB0 = (PRO == PRO_RESID || (PRO == PRO_DIV && sizeof(TO) == 4)) ? 2 : 4;
         constexpr int RB = (NL % RB0 == 0) ? RB0 : ((NL % 2 == 0) ? 2 : 1);
         ColNb cn[CPR];
         int lp[CPR];
