@@ -39,9 +39,9 @@ SLOT_KERNEL = {
     "fp32_refine": {"xfwd": "k_xfwd<double, float, 1, 2048, 256, 512>", "yfwd": "k_yfwd<float, 8192, 1024, 512>",
                     "zsolve": "k_zsolvev<float, float, 4, 16, 24, 512>", "yinv": "k_yinv<float, 8192, 1024, 512>",
                     "xinv": "k_xinv<float, double, 0, 2048, 256, 512>", "xinv_acc": "k_xinv<float, double, 1, 2048, 256, 512>",
-                    "resid": "k_resid_pairs<256, 8, true>", "resid_norm": "k_resid_pairs<256, 8, false>",
+                    "resid": "k_resid_pairs<256, 8, true, float>", "resid_norm": "k_resid_pairs<256, 8, false, double>",
                     "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256>",
-                    "grad_resid": "k_grad_resid<256, 8, false>"},
+                    "grad_resid": "k_grad_resid<256, 16, false>"},
 }
 
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:

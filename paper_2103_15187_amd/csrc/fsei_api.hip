@@ -117,6 +117,17 @@ long xblocks(const fsei_plan* p) {
     return ((long)p->ny * p->nz + nl - 1) / nl;
 }
 
+// Row tile of the fused gradient + residual kernel (16 when ny allows, else
+// 8; 8 is forced with FSEI_GR_ROWS=8 for measurement).  The residual-only
+// kernel stays at 8 rows (measured faster there).
+int gr_rows() {
+    static int v = [] {
+        const char* e = getenv("FSEI_GR_ROWS");
+        return e ? atoi(e) : 16;
+    }();
+    return v;
+}
+
 // Gradient kernel selection: 0 = one row per workgroup, one cell pair per
 // lane (nx even, <= 512, ny % 8 == 0); 1 = tiles of 8 rows, cell pairs;
 // 2 = one row per workgroup, one cell per lane.  FSEI_GRAD_CFG overrides the
@@ -555,10 +566,22 @@ long launch_grad_resid(fsei_plan* p, double* u, double* v, double* w, const doub
     a.zc = tab<double>(p, T_ZC);
     a.scal = scalars(p);
     a.partials = partials(p);
-    const long nb = (long)(p->ny / kPairRows) * p->nz;
+    // 16-row tiles halve the re-read halo rows (j-1 of the first row, j+1 of
+    // the last) against 8-row tiles when ny allows
+    const int rows = (gr_rows() == 16 && p->ny % 16 == 0) ? 16 : kPairRows;
+    const long nb = (long)(p->ny / rows) * p->nz;
     const dim3 grid((unsigned)nb);
     const int np = p->nx / 2;
     Timed t(p, K_GRAD_RESID);
+    if (rows == 16) {
+        if (np >= 256)
+            hipLaunchKernelGGL((k_grad_resid<256, 16, DELTA>), grid, dim3(256), 0, S(p), a);
+        else if (np > 64)
+            hipLaunchKernelGGL((k_grad_resid<128, 16, DELTA>), grid, dim3(128), 0, S(p), a);
+        else
+            hipLaunchKernelGGL((k_grad_resid<64, 16, DELTA>), grid, dim3(64), 0, S(p), a);
+        return nb;
+    }
     if (np >= 256)
         hipLaunchKernelGGL((k_grad_resid<256, kPairRows, DELTA>), grid, dim3(256), 0, S(p), a);
     else if (np > 64)
