@@ -117,9 +117,10 @@ long xblocks(const fsei_plan* p) {
     return ((long)p->ny * p->nz + nl - 1) / nl;
 }
 
-// Row tile of the fused gradient + residual kernel (16 when ny allows, else
-// 8; 8 is forced with FSEI_GR_ROWS=8 for measurement).  The residual-only
-// kernel stays at 8 rows (measured faster there).
+// Row tile of the fused gradient + residual kernel and of the gradient's
+// row order (16 when ny allows, else 8; 8 is forced with FSEI_GR_ROWS=8 for
+// measurement).  The residual-only kernel stays at 8 rows (measured faster
+// there).
 int gr_rows() {
     static int v = [] {
         const char* e = getenv("FSEI_GR_ROWS");
@@ -474,12 +475,21 @@ void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoin
     if (grad_cfg() == 0 && p->nx % 2 == 0 && p->nx <= 512 && p->ny % 8 == 0 && al) {
         const dim3 grid((unsigned)((long)p->ny * p->nz));
         const int np = p->nx / 2;
+        if (p->ny % 16 == 0 && gr_rows() == 16) {
+            if (np > 128)
+                hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256, 16>), grid, dim3(256), 0, S(p), a);
+            else if (np > 64)
+                hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128, 16>), grid, dim3(128), 0, S(p), a);
+            else
+                hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64, 16>), grid, dim3(64), 0, S(p), a);
+            return;
+        }
         if (np > 128)
-            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256>), grid, dim3(256), 0, S(p), a);
+            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256, 8>), grid, dim3(256), 0, S(p), a);
         else if (np > 64)
-            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128>), grid, dim3(128), 0, S(p), a);
+            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128, 8>), grid, dim3(128), 0, S(p), a);
         else
-            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64>), grid, dim3(64), 0, S(p), a);
+            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64, 8>), grid, dim3(64), 0, S(p), a);
         return;
     }
     if (grad_cfg() == 1 && pair_tiles(p) && al) {

@@ -704,12 +704,11 @@ __global__ __launch_bounds__(NT) void k_grad_pairs(GradArgs<TIO, TP> a) {
 
 // One x-row per workgroup, one cell pair per lane (NT >= nx / 2): the
 // simplest streaming shape, which runs closest to the HBM ceiling.  Rows in
-// tiles of GJ rows, plane by plane inside a tile (as k_grad).
-template <typename TIO, typename TP, int NT>
+// tiles of GJ rows (ny % GJ == 0), plane by plane inside a tile (as k_grad).
+template <typename TIO, typename TP, int NT, int GJ>
 __global__ __launch_bounds__(NT) void k_grad_row2(GradArgs<TIO, TP> a) {
     using V = typename Vec2T<TIO>::type;
     using VP = typename Vec2T<TP>::type;
-    constexpr int GJ = 8;
     const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
     const int nx = a.nx, ny = a.ny;
     const int per = a.nz * GJ;
