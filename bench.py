@@ -48,8 +48,11 @@ SLOT_KERNEL = {
 # every operand read once, every result written once).
 BYTES_PER_CELL = {
     "fp64": {"xfwd": 32, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "grad": 56},
-    "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 12, "resid_xfwd": 20,
-                    "resid": 20, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 20, "grad": 56, "grad_resid": 64},
+    # refinement at this workload (pair tiling): the first solve's pressure is
+    # FP32 (x inverse writes 4 B; the first residual reads it: f 8 + p 4, r 4
+    # written; the first correction reads p32 + delta and writes p 8)
+    "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 8, "resid_xfwd": 20,
+                    "resid": 16, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 16, "grad": 56, "grad_resid": 64},
 }
 
 
