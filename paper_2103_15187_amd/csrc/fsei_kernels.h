@@ -247,10 +247,11 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
 // streams markedly better from HBM than 128-B segments; the M lines'
 // recurrences also interleave.  Dense mode only; needs nx % M == 0.
 // ---------------------------------------------------------------------------
+// M adjacent values as one native vector (one 8- or 16-byte access)
 template <typename T, int M> struct VecM;
-template <> struct VecM<double, 2> { using type = double2; };
-template <> struct VecM<float, 2> { using type = float2; };
-template <> struct VecM<float, 4> { using type = float4; };
+template <> struct VecM<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecM<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct VecM<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
 
 template <typename TS, typename TC, int M, int TXLM, int L, int NT>
 __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
@@ -293,17 +294,17 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
     const bool inrange = p < P;
     const int s0 = inrange ? p * L : 0;
     const bool anyact = anyl && inrange;
-    V* __restrict__ col = reinterpret_cast<V*>(a.data + (size_t)qy * nx + (qx0 < nx ? qx0 : 0));
+    const size_t coff = (size_t)qy * nx + (qx0 < nx ? qx0 : 0);   // element offset of the lane's column
+    const V* __restrict__ col = reinterpret_cast<const V*>(a.data + coff);
 
     TC F[M][L], Rr[M][L];
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         const int k = s0 + t;
-        V v{};
+        V v = (V)(TS)0;
         if (anyact && k < nz) v = col[(size_t)k * strideV];
-        const TS* e = reinterpret_cast<const TS*>(&v);
 #pragma unroll
-        for (int h = 0; h < M; ++h) F[h][t] = (TC)e[h];
+        for (int h = 0; h < M; ++h) F[h][t] = (TC)v[h];
     }
     __syncthreads();
 #pragma unroll
@@ -434,18 +435,20 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
         }
     }
     if (anyact) {
-        V* out = col + (size_t)s0 * strideV;
-        asm volatile("" : "+v"(out));
-        TS* outs = reinterpret_cast<TS*>(out);
+        // store addresses rebuilt from the field base (not kept live from the
+        // loads), as whole-vector global stores
+        size_t ooff = coff + (size_t)s0 * strideV * M;
+        asm volatile("" : "+v"(ooff));
+        V* out = reinterpret_cast<V*>(a.data + ooff);
+        TS* outs = a.data + ooff;
 #pragma unroll
         for (int t = 0; t < L; ++t) {
             if (s0 + t < nz) {
                 const TC so = tso[s0 + t];
                 if (alll) {
                     V v;
-                    TS* e = reinterpret_cast<TS*>(&v);
 #pragma unroll
-                    for (int h = 0; h < M; ++h) e[h] = (TS)(F[h][t] * so);
+                    for (int h = 0; h < M; ++h) v[h] = (TS)(F[h][t] * so);
                     out[(size_t)t * strideV] = v;
                 } else {
 #pragma unroll

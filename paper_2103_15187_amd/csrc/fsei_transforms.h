@@ -114,14 +114,13 @@ __device__ __forceinline__ void post_fwd(const T* re, const T* im, int s, int SP
 // inverse pre-processing: complex input Z[m] of the pair from the rows m and
 // N-m of the two transformed lines
 template <typename T>
-__device__ __forceinline__ void pre_inv(int N, int m, int bc, T xam, T xanm, T xbm, T xbnm,
-                                        const T* __restrict__ dctc, const T* __restrict__ dcts, T& zr, T& zi) {
+__device__ __forceinline__ void pre_inv_cs(int N, int m, int bc, T xam, T xanm, T xbm, T xbnm, T c, T s, T& zr,
+                                           T& zi) {
     if (bc == FSEI_BC_WALL) {
         if (m == 0) {
             xanm = (T)0;
             xbnm = (T)0;
         }
-        const T c = dctc[m], s = dcts[m];
         const T var = c * xam + s * xanm, vai = s * xam - c * xanm;
         const T vbr = c * xbm + s * xbnm, vbi = s * xbm - c * xbnm;
         zr = var - vbi;
@@ -143,6 +142,18 @@ __device__ __forceinline__ void pre_inv(int N, int m, int bc, T xam, T xanm, T x
         zr = ra - ib;
         zi = ia + rb;
     }
+}
+
+// as pre_inv_cs with the twiddle pair read from the tables
+template <typename T>
+__device__ __forceinline__ void pre_inv(int N, int m, int bc, T xam, T xanm, T xbm, T xbnm,
+                                        const T* __restrict__ dctc, const T* __restrict__ dcts, T& zr, T& zi) {
+    T c = (T)1, s = (T)0;
+    if (bc == FSEI_BC_WALL) {
+        c = dctc[m];
+        s = dcts[m];
+    }
+    pre_inv_cs<T>(N, m, bc, xam, xanm, xbm, xbnm, c, s, zr, zi);
 }
 
 // (k, j) of row j0 + l of plane k0 (rows wrap into the following planes)
@@ -577,11 +588,15 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
     if constexpr (NF > 0) {
         static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
         constexpr int CPR = NF / NTHR;
+        static_assert(CPR % 2 == 0, "paired columns");
+        // each thread loads columns m < NF/2 and its partner NF - m once and
+        // forms both pre-twiddled values (m = 0 pairs with NF/2; both of
+        // those use only their own column)
 #pragma unroll
-        for (int c = 0; c < CPR; ++c) {
+        for (int c = 0; c < CPR / 2; ++c) {
             const int m = threadIdx.x + c * NTHR;
-            const int nm = (m == 0) ? 0 : NF - m;
-            const int lm = li(0, m, SP);
+            const int nm = (m == 0) ? NF / 2 : NF - m;
+            const int lm = li(0, m, SP), lnm = li(0, nm, SP);
             T xam[NSF], xanm[NSF], xbm[NSF], xbnm[NSF];
 #pragma unroll
             for (int s = 0; s < NSF; ++s) {
@@ -590,12 +605,24 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                 xbm[s] = in[(2 * s + 1) * NF + m];
                 xbnm[s] = in[(2 * s + 1) * NF + nm];
             }
+            // cos/sin(pi m / 2NF) at NF - m are sin/cos at m
+            T cm = (T)1, sm = (T)0, cn = (T)1, sn = (T)0;
+            if (a.bcx == FSEI_BC_WALL) {
+                cm = a.dctc[m];
+                sm = a.dcts[m];
+                cn = (m == 0) ? a.dctc[NF / 2] : sm;
+                sn = (m == 0) ? a.dcts[NF / 2] : cm;
+            }
 #pragma unroll
             for (int s = 0; s < NSF; ++s) {
+                const T pa = (m == 0) ? xanm[s] : xam[s], pb = (m == 0) ? xbnm[s] : xbm[s];
                 T zr, zi;
-                pre_inv<T>(NF, m, a.bcx, xam[s], xanm[s], xbm[s], xbnm[s], a.dctc, a.dcts, zr, zi);
+                pre_inv_cs<T>(NF, m, a.bcx, xam[s], xanm[s], xbm[s], xbnm[s], cm, sm, zr, zi);
                 sre[s * SP + lm] = zr;
                 sim[s * SP + lm] = zi;
+                pre_inv_cs<T>(NF, nm, a.bcx, xanm[s], pa, xbnm[s], pb, cn, sn, zr, zi);
+                sre[s * SP + lnm] = zr;
+                sim[s * SP + lnm] = zi;
             }
         }
     } else {
@@ -790,13 +817,13 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
     }
 }
 
-template <typename T, int EMAX, int NTHR, int NF>
+template <typename T, int EMAX, int NTHR, int NF, int PS = kPadShift>
 __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
-    __shared__ T sre[lds_elems(EMAX)];
-    __shared__ T sim[lds_elems(EMAX)];
-    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF) : 0;
+    __shared__ T sre[lds_elems(EMAX, PS)];
+    __shared__ T sim[lds_elems(EMAX, PS)];
+    constexpr int NSF = NF > 0 ? tile_nseq(EMAX, NF, PS) : 0;
     const int N = NF > 0 ? NF : a.ny;
-    const int SP = seq_stride(N);
+    const int SP = seq_stride(N, PS);
     const int nx = a.nx;
     const int nseq = NF > 0 ? NSF : a.nseq;
     const int TX = 2 * nseq;
@@ -811,22 +838,39 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
         static_assert(NTHR % NSF == 0 && NF % RPP == 0 && RPP % 2 == 0, "fixed y tile");
         const int s = threadIdx.x % NSF, mr = threadIdx.x / NSF;
         const unsigned lo = (unsigned)(2 * s);
-        V2 A[NPASS], B[NPASS];
+        // each lane loads rows m < NF/2 and its partner NF - m once and
+        // forms both pre-twiddled values (m = 0 pairs with NF/2; both
+        // of those use only their own row)
+        constexpr int NH = NPASS / 2;
+        static_assert(NPASS % 2 == 0, "paired rows");
+        V2 A[NH], B[NH];
 #pragma unroll
-        for (int r = 0; r < NPASS; ++r) {
+        for (int r = 0; r < NH; ++r) {
             const int m = mr + r * RPP;
-            const int nm = (m == 0) ? 0 : NF - m;
+            const int nm = (m == 0) ? NF / 2 : NF - m;
             A[r] = *reinterpret_cast<const V2*>(d + (size_t)m * nx + lo);
             B[r] = *reinterpret_cast<const V2*>(d + (size_t)nm * nx + lo);
         }
 #pragma unroll
-        for (int r = 0; r < NPASS; ++r) {
+        for (int r = 0; r < NH; ++r) {
             const int m = mr + r * RPP;
+            const int nm = (m == 0) ? NF / 2 : NF - m;
+            const V2 Am = (m == 0) ? B[r] : A[r];
+            // cos/sin(pi m / 2NF) at NF - m are sin/cos at m
+            T c = (T)1, sn = (T)0, cp = (T)1, sp = (T)0;
+            if (a.bcy == FSEI_BC_WALL) {
+                c = a.dctc[m];
+                sn = a.dcts[m];
+                cp = (m == 0) ? a.dctc[NF / 2] : sn;
+                sp = (m == 0) ? a.dcts[NF / 2] : c;
+            }
             T zr, zi;
-            pre_inv<T>(NF, m, a.bcy, A[r].x, B[r].x, A[r].y, B[r].y, a.dctc, a.dcts, zr, zi);
-            const int o = s * SP + li(0, m, SP);
-            sre[o] = zr;
-            sim[o] = zi;
+            pre_inv_cs<T>(NF, m, a.bcy, A[r].x, B[r].x, A[r].y, B[r].y, c, sn, zr, zi);
+            sre[s * SP + li<PS>(0, m, SP)] = zr;
+            sim[s * SP + li<PS>(0, m, SP)] = zi;
+            pre_inv_cs<T>(NF, nm, a.bcy, B[r].x, Am.x, B[r].y, Am.y, cp, sp, zr, zi);
+            sre[s * SP + li<PS>(0, nm, SP)] = zr;
+            sim[s * SP + li<PS>(0, nm, SP)] = zi;
         }
     } else {
         constexpr int PLD = EMAX / NTHR;
@@ -848,13 +892,13 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
                 }
                 T zr, zi;
                 pre_inv<T>(N, m, a.bcy, xam, xanm, xbm, xbnm, a.dctc, a.dcts, zr, zi);
-                sre[li(s, m, SP)] = zr;
-                sim[li(s, m, SP)] = zi;
+                sre[li<PS>(s, m, SP)] = zr;
+                sim[li<PS>(s, m, SP)] = zi;
             }
         }
     }
     __syncthreads();
-    fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
+    fft_lds<T, EMAX, NTHR, 1, NF, PS>(sre, sim, N, nseq, a.fp, twl, twl + N);
     if constexpr (NF > 0) {
         using V2 = typename Vec2T<T>::type;
         constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
@@ -863,7 +907,7 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < NPASS; ++r) {
             const int j = jr + r * RPP;
-            const int o = s * SP + li(0, (a.bcy == FSEI_BC_WALL) ? mk_pos(j, NF) : j, SP);
+            const int o = s * SP + li<PS>(0, (a.bcy == FSEI_BC_WALL) ? mk_pos(j, NF) : j, SP);
             V2 res;
             res.x = sre[o];
             res.y = sim[o];
@@ -879,7 +923,7 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
                 const int c = e - j * TX;
                 if (i0 + c < nx) {
                     const int n = (a.bcy == FSEI_BC_WALL) ? mk_pos(j, N) : j;
-                    d[j * nx + c] = (c & 1) ? sim[li(c >> 1, n, SP)] : sre[li(c >> 1, n, SP)];
+                    d[j * nx + c] = (c & 1) ? sim[li<PS>(c >> 1, n, SP)] : sre[li<PS>(c >> 1, n, SP)];
                 }
             }
         }
