@@ -146,6 +146,7 @@ int grad_cfg() {
 constexpr int kPairRows = 8;
 bool pair_tiles(const fsei_plan* p) { return p->nx % 2 == 0 && p->ny % kPairRows == 0; }
 bool aligned16(const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; }
+bool al16(const void* q) { return q == nullptr || aligned16(q); }   // optional pointer
 
 // the fixed-length x kernels (NF = 512) need every tile of rows full and
 // inside one z-plane
@@ -172,8 +173,11 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
     a.dctc = tab<TO>(p, T_DCTX_C);
     a.dcts = tab<TO>(p, T_DCTX_S);
     const size_t dyn = 2 * p->nx * sizeof(TO);
+    // the fixed path reads and writes every field as aligned column pairs
+    const bool al = al16(a.u) && al16(a.v) && al16(a.w) && al16(a.gp) && al16(a.f) && al16(a.src) && al16(a.p) &&
+                    al16(a.out) && al16(a.out_f);
     Timed t(p, slot);
-    if (x_fixed(p))
+    if (x_fixed(p) && al)
         hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
     else
         hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
@@ -197,8 +201,9 @@ void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add3
     a.dctc = tab<T>(p, T_DCTX_C);
     a.dcts = tab<T>(p, T_DCTX_S);
     const size_t dyn = 2 * p->nx * sizeof(T);
+    const bool al = al16(in) && al16(out) && al16(add32) && al16(keep);
     Timed t(p, slot);
-    if (x_fixed(p))
+    if (x_fixed(p) && al)
         hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
     else
         hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);

@@ -777,9 +777,8 @@ __device__ __forceinline__ double2 ld2d(const T* q) {
     return make_double2((double)v.x, (double)v.y);
 }
 
-template <int NT, int RJ, bool WRITE, typename TPP>
+template <int NT, int RJ, bool WRITE, typename TPP, int RB = 2>   // RB: rows per load batch
 __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
-    constexpr int RB = 4;   // rows per load batch
     static_assert(RJ % RB == 0, "whole batches");
     __shared__ double sred[3 * (NT / 64)];
     const int nx = a.nx, ny = a.ny, nz = a.nz;

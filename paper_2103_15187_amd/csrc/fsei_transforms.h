@@ -380,6 +380,86 @@ __device__ __forceinline__ TI x_prologue_row(const XFwdArgs<TI, TO>& a, size_t r
     }
 }
 
+// x neighbours of the adjacent cells (i, i + 1), i even: i - 1 of the first
+// and i + 2 of the second (wrapped; the flags say whether they take part)
+struct PairNb {
+    unsigned i, im, ip2;
+    bool him, hip2;
+};
+__device__ __forceinline__ PairNb pair_nb(int i, int N, int bcx) {
+    const bool per = bcx == FSEI_BC_PERIODIC;
+    PairNb c;
+    c.i = (unsigned)i;
+    c.im = (i >= 1) ? (unsigned)(i - 1) : (unsigned)(N - 1);
+    c.ip2 = (i + 2 < N) ? (unsigned)(i + 2) : 0u;
+    c.him = (i >= 1) || per;
+    c.hip2 = (i + 2 < N) || per;
+    return c;
+}
+
+// x_prologue_row for the two adjacent cells (i, i + 1) of a row, every
+// field read as aligned pairs (the scalar x neighbours aside)
+template <typename TI, typename TO, int PRO>
+__device__ __forceinline__ void x_prologue_pair(const XFwdArgs<TI, TO>& a, size_t ro, int k, const RowNb& rn,
+                                                const PairNb& cn, TI& v0, TI& v1) {
+    using V = typename Vec2T<TI>::type;
+    if constexpr (PRO == PRO_COPY) {
+        const double2 f = *reinterpret_cast<const double2*>(a.f + ro + cn.i);
+        v0 = (TI)f.x;
+        v1 = (TI)f.y;
+    } else if constexpr (PRO == PRO_SRC) {
+        const V q = *reinterpret_cast<const V*>(a.src + ro + cn.i);
+        v0 = q.x;
+        v1 = q.y;
+    } else if constexpr (PRO == PRO_RESID) {
+        const double* __restrict__ p = a.p + ro;
+        const double2 pc = *reinterpret_cast<const double2*>(p + cn.i);
+        const double pxm = p[cn.im], pxp = p[cn.ip2];
+        const double2 pyp = *reinterpret_cast<const double2*>(p + rn.yp + cn.i);
+        const double2 pym = *reinterpret_cast<const double2*>(p + rn.ym + cn.i);
+        const double2 pzp = *reinterpret_cast<const double2*>(p + rn.zp + cn.i);
+        const double2 pzm = *reinterpret_cast<const double2*>(p + rn.zm + cn.i);
+        const double2 fc = *reinterpret_cast<const double2*>(a.f + ro + cn.i);
+        const double lx0 = (pc.y - pc.x) + (cn.him ? pxm - pc.x : 0.0);
+        const double lx1 = (cn.hip2 ? pxp - pc.y : 0.0) + (pc.x - pc.y);
+        const double ly0 = (rn.hyp ? pyp.x - pc.x : 0.0) + (rn.hym ? pym.x - pc.x : 0.0);
+        const double ly1 = (rn.hyp ? pyp.y - pc.y : 0.0) + (rn.hym ? pym.y - pc.y : 0.0);
+        const double zc = a.zc[k], za = a.za[k];
+        const double lz0 = (rn.hzp ? zc * (pzp.x - pc.x) : 0.0) + (rn.hzm ? za * (pzm.x - pc.x) : 0.0);
+        const double lz1 = (rn.hzp ? zc * (pzp.y - pc.y) : 0.0) + (rn.hzm ? za * (pzm.y - pc.y) : 0.0);
+        const double mean = a.scal[0];
+        v0 = (TI)((fc.x - mean) - (lx0 * a.idx2 + ly0 * a.idy2 + lz0));
+        v1 = (TI)((fc.y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1));
+    } else {
+        const TI zero = (TI)0;
+        const TI* __restrict__ u = a.u + ro;
+        const TI* __restrict__ v = a.v + ro;
+        const TI* __restrict__ w = a.w + ro;
+        const V uc = *reinterpret_cast<const V*>(u + cn.i);
+        const TI uh = u[cn.ip2];
+        const V vc = *reinterpret_cast<const V*>(v + cn.i);
+        const V vh = *reinterpret_cast<const V*>(v + rn.yp + cn.i);
+        const V wc = *reinterpret_cast<const V*>(w + cn.i);
+        const V wh = *reinterpret_cast<const V*>(w + rn.zp + cn.i);
+        const TI zk = a.zeta[k], ek = a.eta[k];
+        TI r0 = (uc.y - (cn.him ? uc.x : zero)) * a.idx + ((rn.hyp ? vh.x : zero) - (rn.hym ? vc.x : zero)) * a.idy +
+                (zk * (rn.hzp ? wh.x : zero) - ek * (rn.hzm ? wc.x : zero));
+        TI r1 = ((cn.hip2 ? uh : zero) - uc.y) * a.idx + ((rn.hyp ? vh.y : zero) - (rn.hym ? vc.y : zero)) * a.idy +
+                (zk * (rn.hzp ? wh.y : zero) - ek * (rn.hzm ? wc.y : zero));
+        r0 *= a.alpha;
+        r1 *= a.alpha;
+        if constexpr (PRO == PRO_DIV_ADJ) {
+            if (a.gp) {
+                const V g = *reinterpret_cast<const V*>(a.gp + ro + cn.i);
+                r0 += a.beta * g.x;
+                r1 += a.beta * g.y;
+            }
+        }
+        v0 = r0;
+        v1 = r1;
+    }
+}
+
 template <typename TI, typename TO, int PRO, int EMAX, int NTHR, int NF>
 __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
     __shared__ TO sre[lds_elems(EMAX)];
@@ -418,17 +498,21 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
         // two rows keep its registers within four waves per SIMD)
         constexpr int RB0 = (PRO == PRO_RESID || (PRO == PRO_DIV && sizeof(TO) == 4)) ? 2 : 4;
         constexpr int RB = (NL % RB0 == 0) ? RB0 : ((NL % 2 == 0) ? 2 : 1);
-        ColNb cn[CPR];
-        int lp[CPR];
+        // each thread owns the adjacent columns (2q, 2q + 1), q = tid + c NTHR
+        constexpr int PPR = CPR / 2;
+        static_assert(CPR % 2 == 0, "column pairs");
+        PairNb cn[PPR];
+        int lp0[PPR], lp1[PPR];
 #pragma unroll
-        for (int c = 0; c < CPR; ++c) {
-            const int i = threadIdx.x + c * NTHR;
-            cn[c] = col_nb(i, NF, a.bcx);
-            lp[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
+        for (int c = 0; c < PPR; ++c) {
+            const int i = 2 * (threadIdx.x + c * NTHR);
+            cn[c] = pair_nb(i, NF, a.bcx);
+            lp0[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
+            lp1[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i + 1, NF) : i + 1, SP);
         }
 #pragma unroll
         for (int l0 = 0; l0 < NL; l0 += RB) {
-            TI val[RB][CPR];
+            TI val0[RB][PPR], val1[RB][PPR];
 #pragma unroll
             for (int lr = 0; lr < RB; ++lr) {
                 // the host launches this path only when ny is a multiple of
@@ -436,20 +520,21 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
                 const int l = l0 + lr;
                 const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
 #pragma unroll
-                for (int c = 0; c < CPR; ++c)
-                    val[lr][c] = x_prologue_row<TI, TO, PRO>(a, base + (size_t)l * NF, k0, rn, cn[c]);
+                for (int c = 0; c < PPR; ++c)
+                    x_prologue_pair<TI, TO, PRO>(a, base + (size_t)l * NF, k0, rn, cn[c], val0[lr][c], val1[lr][c]);
             }
 #pragma unroll
             for (int lr = 0; lr < RB; ++lr) {
                 const int l = l0 + lr;
 #pragma unroll
-                for (int c = 0; c < CPR; ++c) {
-                    const double v = (double)val[lr][c];
-                    if (out_f) out_f[base + (size_t)l * NF + cn[c].i] = v;
-                    ss += v * v;
-                    s1 += v;
+                for (int c = 0; c < PPR; ++c) {
+                    const double v0 = (double)val0[lr][c], v1 = (double)val1[lr][c];
+                    if (out_f) *reinterpret_cast<double2*>(out_f + base + (size_t)l * NF + cn[c].i) = make_double2(v0, v1);
+                    ss += v0 * v0 + v1 * v1;
+                    s1 += v0 + v1;
                     TO* dst = (l & 1) ? sim : sre;
-                    dst[(l >> 1) * SP + lp[c]] = (TO)val[lr][c];
+                    dst[(l >> 1) * SP + lp0[c]] = (TO)val0[lr][c];
+                    dst[(l >> 1) * SP + lp1[c]] = (TO)val1[lr][c];
                 }
             }
         }
@@ -511,25 +596,31 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
     fft_lds<TO, EMAX, NTHR, -1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
     TO* __restrict__ out = a.out + base;
     if constexpr (NF > 0) {
-        constexpr int CPR = NF / NTHR;
+        // outputs m, m + 1 (m even) of every line pair, stored as pairs
+        using VO = typename Vec2T<TO>::type;
+        constexpr int PPR = NF / NTHR / 2;
 #pragma unroll
-        for (int c = 0; c < CPR; ++c) {
-            const int m = threadIdx.x + c * NTHR;
-            const int mm = (m == 0) ? 0 : NF - m;
-            const int lm = li(0, m, SP), lmm = li(0, mm, SP);
-            const bool lo = 2 * m <= NF;
-            TO wr = (TO)1, wi = (TO)0;
+        for (int c = 0; c < PPR; ++c) {
+            const int m0 = 2 * (threadIdx.x + c * NTHR), m1 = m0 + 1;
+            const int mm0 = (m0 == 0) ? 0 : NF - m0, mm1 = NF - m1;
+            const int l0 = li(0, m0, SP), lm0 = li(0, mm0, SP), l1 = li(0, m1, SP), lm1 = li(0, mm1, SP);
+            const bool lo0 = 2 * m0 <= NF, lo1 = 2 * m1 <= NF;
+            TO wr0 = (TO)1, wi0 = (TO)0, wr1 = (TO)1, wi1 = (TO)0;
             if (a.bcx == FSEI_BC_WALL) {
-                wr = a.dctc[m];
-                wi = -a.dcts[m];
+                wr0 = a.dctc[m0];
+                wi0 = -a.dcts[m0];
+                wr1 = a.dctc[m1];
+                wi1 = -a.dcts[m1];
             }
 #pragma unroll
             for (int s = 0; s < NSF; ++s) {
-                TO xa, xb;
-                post_fwd_v<TO>(a.bcx, lo, sre[s * SP + lm], sim[s * SP + lm], sre[s * SP + lmm], sim[s * SP + lmm],
-                               wr, wi, xa, xb);
-                out[(2 * s) * NF + m] = xa;
-                out[(2 * s + 1) * NF + m] = xb;
+                VO xa, xb;
+                post_fwd_v<TO>(a.bcx, lo0, sre[s * SP + l0], sim[s * SP + l0], sre[s * SP + lm0], sim[s * SP + lm0],
+                               wr0, wi0, xa.x, xb.x);
+                post_fwd_v<TO>(a.bcx, lo1, sre[s * SP + l1], sim[s * SP + l1], sre[s * SP + lm1], sim[s * SP + lm1],
+                               wr1, wi1, xa.y, xb.y);
+                *reinterpret_cast<VO*>(out + (2 * s) * NF + m0) = xa;
+                *reinterpret_cast<VO*>(out + (2 * s + 1) * NF + m0) = xb;
             }
         }
     } else {
@@ -654,37 +745,60 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
     fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
     TP* __restrict__ out = a.out + base;
     if constexpr (NF > 0) {
-        constexpr int CPR = NF / NTHR, NL = 2 * NSF;
-        int ln[CPR];
+        // outputs i, i + 1 (i even) of every line, read and written as pairs
+        using VT = typename Vec2T<T>::type;
+        using VP = typename Vec2T<TP>::type;
+        constexpr int PPR = NF / NTHR / 2, NL = 2 * NSF;
+        static_assert(NF % (2 * NTHR) == 0, "column pairs");
+        int ln0[PPR], ln1[PPR];
 #pragma unroll
-        for (int c = 0; c < CPR; ++c) {
-            const int i = threadIdx.x + c * NTHR;
-            ln[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
+        for (int c = 0; c < PPR; ++c) {
+            const int i = 2 * (threadIdx.x + c * NTHR);
+            ln0[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
+            ln1[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i + 1, NF) : i + 1, SP);
         }
         if constexpr (EPI == EPI_ACC || EPI == EPI_ADDF || EPI == EPI_ACC_KEEP) {
-            TP old[NL][CPR];
+            VP old[NL][PPR];
             const float* __restrict__ add = (EPI == EPI_ADDF) ? a.add32 + base : nullptr;
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
-                for (int c = 0; c < CPR; ++c)
-                    old[l][c] = (EPI == EPI_ADDF) ? (TP)add[l * NF + threadIdx.x + c * NTHR]
-                                                  : out[l * NF + threadIdx.x + c * NTHR];
+                for (int c = 0; c < PPR; ++c) {
+                    const int o = l * NF + 2 * (threadIdx.x + c * NTHR);
+                    if constexpr (EPI == EPI_ADDF) {
+                        const float2 q = *reinterpret_cast<const float2*>(add + o);
+                        old[l][c].x = (TP)q.x;
+                        old[l][c].y = (TP)q.y;
+                    } else {
+                        old[l][c] = *reinterpret_cast<const VP*>(out + o);
+                    }
+                }
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
-                for (int c = 0; c < CPR; ++c) {
-                    const T val = (l & 1) ? sim[(l >> 1) * SP + ln[c]] : sre[(l >> 1) * SP + ln[c]];
-                    out[l * NF + threadIdx.x + c * NTHR] = old[l][c] + (TP)val;
-                    if constexpr (EPI == EPI_ACC_KEEP) a.keep[base + l * NF + threadIdx.x + c * NTHR] = val;
+                for (int c = 0; c < PPR; ++c) {
+                    const int o = l * NF + 2 * (threadIdx.x + c * NTHR);
+                    const T* src = (l & 1) ? sim : sre;
+                    VT val;
+                    val.x = src[(l >> 1) * SP + ln0[c]];
+                    val.y = src[(l >> 1) * SP + ln1[c]];
+                    VP r;
+                    r.x = old[l][c].x + (TP)val.x;
+                    r.y = old[l][c].y + (TP)val.y;
+                    *reinterpret_cast<VP*>(out + o) = r;
+                    if constexpr (EPI == EPI_ACC_KEEP) *reinterpret_cast<VT*>(a.keep + base + o) = val;
                 }
         } else {
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
-                for (int c = 0; c < CPR; ++c) {
-                    const T val = (l & 1) ? sim[(l >> 1) * SP + ln[c]] : sre[(l >> 1) * SP + ln[c]];
-                    out[l * NF + threadIdx.x + c * NTHR] = (TP)val;
+                for (int c = 0; c < PPR; ++c) {
+                    const int o = l * NF + 2 * (threadIdx.x + c * NTHR);
+                    const T* src = (l & 1) ? sim : sre;
+                    VP r;
+                    r.x = (TP)src[(l >> 1) * SP + ln0[c]];
+                    r.y = (TP)src[(l >> 1) * SP + ln1[c]];
+                    *reinterpret_cast<VP*>(out + o) = r;
                 }
         }
     } else {
