@@ -656,8 +656,22 @@ void reduce_partials(fsei_plan* p, int off, bool vmean = false, long nblk = -1) 
     Timed t(p, K_NORM);
     const double scale = 1.0 / ((double)p->nx * (double)p->ny * p->lz);
     if (nblk < 0) nblk = xblocks(p);
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, S(p), (const double*)partials(p), (int)nblk,
-                       scalars(p) + off, vmean ? scalars(p) : nullptr, scale);
+    double* out = scalars(p) + off;
+    double* mean = vmean ? scalars(p) : nullptr;
+    if (nblk <= 4 * kSumGroups) {
+        hipLaunchKernelGGL(k_sum_partials<1024>, dim3(1), dim3(1024), 0, S(p), (const double*)partials(p), (int)nblk,
+                           out, mean, scale);
+        return;
+    }
+    // two stages: kSumGroups workgroups over contiguous chunks, then one
+    // small workgroup over their triples (the group sums follow the
+    // partials in the workspace)
+    const int chunk = (int)((nblk + kSumGroups - 1) / kSumGroups);
+    double* grp = partials(p) + 3 * p->n_partials;
+    hipLaunchKernelGGL(k_sum_partials_grp, dim3(kSumGroups), dim3(256), 0, S(p), (const double*)partials(p),
+                       (int)nblk, chunk, grp);
+    hipLaunchKernelGGL(k_sum_partials<64>, dim3(1), dim3(64), 0, S(p), (const double*)grp, kSumGroups, out, mean,
+                       scale);
 }
 
 // ---------------------------------------------------------------------------

@@ -998,18 +998,19 @@ __global__ __launch_bounds__(256) void k_widen(const float* __restrict__ in, dou
         out[i] = (double)in[i];
 }
 
-// deterministic sum of the per-block partial triples (one workgroup of 1024
-// threads, 8 blocks' triples in flight per thread, fixed summation order);
-// optionally also mean_out = (third sum) * mean_scale
-__global__ __launch_bounds__(1024) void k_sum_partials(const double* part, int nblk, double* out, double* mean_out,
-                                                      double mean_scale) {
-    __shared__ double sh[3 * 16];
+// deterministic sum of the per-block partial triples: one workgroup of NT
+// threads, 8 triples in flight per thread, fixed summation order; optionally
+// also mean_out = (third sum) * mean_scale
+template <int NT>
+__global__ __launch_bounds__(NT) void k_sum_partials(const double* part, int nblk, double* out, double* mean_out,
+                                                    double mean_scale) {
+    __shared__ double sh[3 * (NT / 64)];
     double a = 0.0, b = 0.0, c = 0.0;
-    for (int t0 = threadIdx.x; t0 < nblk; t0 += 8 * 1024) {
+    for (int t0 = threadIdx.x; t0 < nblk; t0 += 8 * NT) {
         double v[8][3];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int t = t0 + r * 1024;
+            const int t = t0 + r * NT;
 #pragma unroll
             for (int q = 0; q < 3; ++q) v[r][q] = (t < nblk) ? part[3 * t + q] : 0.0;
         }
@@ -1020,12 +1021,42 @@ __global__ __launch_bounds__(1024) void k_sum_partials(const double* part, int n
             c += v[r][2];
         }
     }
-    block_sum3<1024>(a, b, c, sh);
+    block_sum3<NT>(a, b, c, sh);
     if (threadIdx.x == 0) {
         out[0] = a;
         out[1] = b;
         out[2] = c;
         if (mean_out) *mean_out = c * mean_scale;
+    }
+}
+
+// first stage of the two-stage sum: workgroup g sums the triples
+// [g * chunk, min(nblk, (g + 1) * chunk)) in a fixed order into grp[3 g ..]
+__global__ __launch_bounds__(256) void k_sum_partials_grp(const double* part, int nblk, int chunk, double* grp) {
+    __shared__ double sh[3 * 4];
+    const int lo = blockIdx.x * chunk;
+    const int hi = (lo + chunk < nblk) ? lo + chunk : nblk;
+    double a = 0.0, b = 0.0, c = 0.0;
+    for (int t0 = lo + (int)threadIdx.x; t0 < hi; t0 += 4 * 256) {
+        double v[4][3];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = t0 + r * 256;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) v[r][q] = (t < hi) ? part[3 * t + q] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a += v[r][0];
+            b += v[r][1];
+            c += v[r][2];
+        }
+    }
+    block_sum3<256>(a, b, c, sh);
+    if (threadIdx.x == 0) {
+        grp[3 * blockIdx.x] = a;
+        grp[3 * blockIdx.x + 1] = b;
+        grp[3 * blockIdx.x + 2] = c;
     }
 }
 

@@ -70,7 +70,7 @@ void compute_layout(fsei_plan_impl* p) {
     p->ws_scalars = off;
     off = round_up(off + fsei_plan_impl::kScalars * sizeof(double), kAlign);
     p->ws_partials = off;
-    off = round_up(off + 3 * p->n_partials * sizeof(double), kAlign);
+    off = round_up(off + 3 * (p->n_partials + kSumGroups) * sizeof(double), kAlign);   // + group sums
     p->ws_list = off;
     p->ws_list_bytes = (size_t)p->nlist * sizeof(int);
     off = round_up(off + p->ws_list_bytes, kAlign);

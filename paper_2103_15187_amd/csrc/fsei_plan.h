@@ -15,6 +15,7 @@ constexpr int kMaxStages = 16;
 constexpr int kMaxN = 2048;     // longest x/y transform
 constexpr int kMaxNz = 2048;    // longest z line
 constexpr size_t kAlign = 256;
+constexpr int kSumGroups = 64;   // first-stage workgroups of the two-stage partial sums
 // complex elements per x-transform workgroup (and 8 per thread): small tiles
 // keep several workgroups resident per CU so loads, LDS transforms and
 // stores of different workgroups overlap
