@@ -1,3 +1,4 @@
-"""FP64 CPU oracle (test infrastructure only; see fsei_oracle.py)."""
+"""FP64 CPU oracle (test infrastructure only; see fsei_oracle.py and viscous_oracle.py)."""
 from .fsei_oracle import *  # noqa: F401,F403
 from .fsei_oracle import Grid, PERIODIC, WALL  # noqa: F401
+from . import viscous_oracle as viscous  # noqa: F401
