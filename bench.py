@@ -43,6 +43,8 @@ SLOT_KERNEL = {
                     "resid_norm": "k_resid_pairs<256, 8, false, double, 2>",
                     "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256, 16>",
                     "grad_resid": "k_grad_resid<256, 16, false>"},
+    "viscous_fp64": {"visc_x": "k_visc_x<16>", "visc_y": "k_visc_strided<2, 16>",
+                     "visc_z": "k_visc_strided<2, 24>"},
 }
 
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:
@@ -54,6 +56,9 @@ BYTES_PER_CELL = {
     # written; the first correction reads p32 + delta and writes p 8)
     "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 8, "resid_xfwd": 20,
                     "resid": 16, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 16, "grad": 56, "grad_resid": 64},
+    # implicit viscous step: every line solve of one component reads and
+    # writes the field once (3 components x 3 directions = 144 B/cell)
+    "viscous_fp64": {"visc_x": 16, "visc_y": 16, "visc_z": 16},
 }
 
 
@@ -108,6 +113,35 @@ def gpu_mode(mode, spec, u0, v0, w0, steps, warmup, torch, fsei):
     del bufs
     torch.cuda.empty_cache()
     return res, plan
+
+
+def gpu_viscous(spec, u0, v0, w0, steps, warmup, torch, fsei):
+    """Time `steps` implicit viscous steps (fsei_viscous_solve of u, v, w) on
+    resident copies of the input (the solve does the same work whatever the
+    values, so each step re-solves the previous step's output)."""
+    plan = fsei.Plan.from_spec(spec)
+    beta = 0.5 * spec.dx ** 2
+    u, v, w = u0.clone(), v0.clone(), w0.clone()
+    for _ in range(warmup):
+        plan.viscous_step(u, v, w, beta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.viscous_step(u, v, w, beta)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nk = min(steps, 3)
+    plan.reset_timing()
+    plan.set_timing(True)
+    for _ in range(nk):
+        plan.viscous_step(u, v, w, beta)
+    torch.cuda.synchronize()
+    plan.set_timing(False)
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": plan.kernel_times(), "kernel_steps": nk,
+           "last_info": None, "div_check": None, "beta": beta}
+    del u, v, w
+    torch.cuda.empty_cache()
+    return res
 
 
 def divergence_max(u, v, w, spec, torch):
@@ -295,6 +329,8 @@ def main():
     ap.add_argument("--config", default="C3")
     ap.add_argument("--modes", default="fp32_refine,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-viscous", action="store_true",
+                    help="skip the implicit viscous step (reported beside the projection, not in value)")
     ap.add_argument("--calib", action="store_true",
                     help="also run torch.neg over one field (a plain streaming kernel of known size: "
                          "reads and writes 8 B per cell) to calibrate hardware byte counters")
@@ -368,6 +404,16 @@ def main():
     }
     for m in modes:
         line["modes"][m]["roofline"] = roofline_for(m, results[m], ncells)
+    if not args.no_viscous:
+        log(f"[bench] viscous step: warmup {args.warmup}, steps {args.steps}")
+        vres = gpu_viscous(spec, u0, v0, w0, args.steps, args.warmup, torch, fsei)
+        log(f"[bench] viscous step: {vres['ms_per_step']:.3f} ms/step")
+        vs = mode_summary("viscous_fp64", vres, ncells)
+        vs.pop("max_abs_div_after", None)
+        vs["steps_per_s"] = vs.pop("solves_per_s")
+        vs["beta"] = vres["beta"]
+        vs["roofline"] = roofline_for("viscous_fp64", vres, ncells)
+        line["modes"]["viscous_fp64"] = vs
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(spec)

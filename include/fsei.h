@@ -149,6 +149,31 @@ fsei_status fsei_project_f32(fsei_plan* plan, float* u, float* v, float* w, floa
 fsei_status fsei_project_backward_f32(fsei_plan* plan, float* gu, float* gv, float* gw, const float* gp,
                                       float dt);
 
+/* Implicit viscous step of one velocity component (paper, Sec. 2.1, eq.
+ * NSdiscr0: Crank-Nicolson for the viscous term; Sec. 3: the 3-D operator is
+ * approximately factorised into one tridiagonal operator per direction,
+ * inverted with Thomas' algorithm and a Sherman-Morrison correction in the
+ * periodic directions).  Solves, in place,
+ *
+ *     (I - beta L_x)(I - beta L_y)(I - beta L_z) dq = rhs,
+ *
+ * x factor first, then y, then z.  L_d is the staggered three-point second
+ * difference of the component along d: along its own axis (u along x, v
+ * along y, w along z) the values are faces, a wall face is Dirichlet zero
+ * (the stored wall face is ignored on input and written 0, the opposite wall
+ * face is not stored); along the other axes the values are cell centres and
+ * a wall is no-slip through a mirrored ghost value; z is stretched (zc of
+ * the plan) and always walled; x and y use the plan's boundary types.
+ *   component : 0 (u), 1 (v), 2 (w)
+ *   q         : device, (nz, ny, nx) FP64; in: rhs, out: dq
+ *   beta      : > 0, finite (dt / (2 Re) for Crank-Nicolson)
+ * Needs the plan's workspace (it holds the line tables) and nx, ny, nz <=
+ * 1024 (FSEI_ERR_SIZE otherwise); works with plans of any precision.  The
+ * first call for a component, and any call with a beta different from that
+ * component's previous one, waits for the plan's stream once and uploads
+ * new tables; otherwise the call only enqueues three kernels. */
+fsei_status fsei_viscous_solve(fsei_plan* plan, int component, double* q, double beta);
+
 /* Per-kernel timing with HIP events on the plan's stream (for measurement).
  * enable != 0 records an event pair around every launch from now on;
  * fsei_plan_reset_timing clears the accumulators. */
@@ -158,7 +183,7 @@ fsei_status fsei_plan_reset_timing(fsei_plan* plan);
 /* Read the accumulated timing of kernel slot `slot` (0 <= slot < FSEI_NUM_KERNEL_SLOTS):
  * total milliseconds and launch count (waits for the stream).  name receives
  * a static string naming the slot's kernel. */
-#define FSEI_NUM_KERNEL_SLOTS 16
+#define FSEI_NUM_KERNEL_SLOTS 20
 fsei_status fsei_plan_kernel_time(fsei_plan* plan, int slot, double* total_ms, long* launches,
                                   const char** name);
 

@@ -11,6 +11,7 @@
 
 #include "fsei_kernels.h"
 #include "fsei_plan.h"
+#include "fsei_viscous.h"
 
 using namespace fsei;
 using namespace fsei::dev;
@@ -21,12 +22,15 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", ""};
+    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "", ""};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
 constexpr int K_RESID_PAIRS = 12;
 constexpr int K_XFWD_R = 13;
 constexpr int K_GRAD_RESID = 14;
+constexpr int K_VISC_X = 15;
+constexpr int K_VISC_Y = 16;
+constexpr int K_VISC_Z = 17;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -634,6 +638,56 @@ fsei_status check_hip() {
     return (hipGetLastError() == hipSuccess) ? FSEI_OK : FSEI_ERR_HIP;
 }
 
+// ---------------------------------------------------------------------------
+// implicit viscous step: line solves along x (LDS-staged), y and z (strided)
+// ---------------------------------------------------------------------------
+template <int L>
+void launch_visc_x_L(fsei_plan* p, const ViscArgs& a) {
+    const long per = (long)kViscXLines * kViscXTiles;
+    const unsigned nb = (unsigned)((a.nlines + per - 1) / per);
+    const int dyn = kViscXLines * (a.n + 2) * (int)sizeof(double);
+    static bool attr = false;   // allow the tile beyond the default dynamic LDS limit
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_visc_x<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  kViscXLines * (kViscMaxN + 2) * (int)sizeof(double));
+        attr = true;
+    }
+    hipLaunchKernelGGL((k_visc_x<L>), dim3(nb), dim3(kViscXLines * kViscPmax), dyn, S(p), a);
+}
+
+void launch_visc_x(fsei_plan* p, const ViscArgs& a, int L) {
+    switch (L) {
+        case 4: launch_visc_x_L<4>(p, a); break;
+        case 8: launch_visc_x_L<8>(p, a); break;
+        case 12: launch_visc_x_L<12>(p, a); break;
+        case 16: launch_visc_x_L<16>(p, a); break;
+        case 24: launch_visc_x_L<24>(p, a); break;
+        default: launch_visc_x_L<32>(p, a); break;
+    }
+}
+
+template <int M>
+void launch_visc_s_M(fsei_plan* p, const ViscArgs& a, int L, unsigned groups) {
+    const dim3 g((unsigned)((a.ncol + 16 * M - 1) / (16 * M)), groups);
+    const dim3 b(16 * kViscPmax);
+    switch (L) {
+        case 4: hipLaunchKernelGGL((k_visc_strided<M, 4>), g, b, 0, S(p), a); break;
+        case 8: hipLaunchKernelGGL((k_visc_strided<M, 8>), g, b, 0, S(p), a); break;
+        case 12: hipLaunchKernelGGL((k_visc_strided<M, 12>), g, b, 0, S(p), a); break;
+        case 16: hipLaunchKernelGGL((k_visc_strided<M, 16>), g, b, 0, S(p), a); break;
+        case 24: hipLaunchKernelGGL((k_visc_strided<M, 24>), g, b, 0, S(p), a); break;
+        default: hipLaunchKernelGGL((k_visc_strided<M, 32>), g, b, 0, S(p), a); break;
+    }
+}
+
+void launch_visc_strided(fsei_plan* p, const ViscArgs& a, int L, unsigned groups) {
+    // two adjacent columns per lane (16-byte accesses) when the rows allow
+    if (a.ncol % 2 == 0 && aligned16(a.data))
+        launch_visc_s_M<2>(p, a, L, groups);
+    else
+        launch_visc_s_M<1>(p, a, L, groups);
+}
+
 fsei_status ready(const fsei_plan* p) {
     if (!p) return FSEI_ERR_ARG;
     if (!p->ws || p->ws_bytes < p->ws_total) return FSEI_ERR_WORKSPACE;
@@ -914,6 +968,7 @@ fsei_status fsei_plan_set_workspace(fsei_plan* p, void* dev, size_t bytes) {
         return FSEI_ERR_HIP;
     p->ws = dev;
     p->ws_bytes = bytes;
+    for (double& b : p->visc_beta) b = 0.0;   // viscous tables live in the workspace: rebuild on next use
     return FSEI_OK;
 }
 
@@ -1045,6 +1100,60 @@ fsei_status fsei_project_backward_f32(fsei_plan* p, float* gu, float* gv, float*
     launch_y<float>(p, buf, true);
     launch_xinv<float, float, EPI_STORE>(p, buf, buf, K_XINV);
     launch_grad<float, float>(p, gu, gv, gw, buf, true, dt);
+    return check_hip();
+}
+
+fsei_status fsei_viscous_solve(fsei_plan* p, int comp, double* q, double beta) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!q || comp < 0 || comp > 2 || !std::isfinite(beta) || !(beta > 0.0)) return FSEI_ERR_ARG;
+    if (p->ws_visc_comp == 0) return FSEI_ERR_SIZE;
+    double* tab = reinterpret_cast<double*>((char*)p->ws + p->ws_visc + comp * p->ws_visc_comp);
+    if (p->visc_beta[comp] != beta) {
+        // new tables for this component: drain the stream first so that no
+        // earlier solve still reads the old ones, and keep the host copy
+        // alive in the plan until the next rebuild (which drains again)
+        if (hipStreamSynchronize(S(p)) != hipSuccess) return FSEI_ERR_HIP;
+        std::vector<double>& h = p->visc_host[comp];
+        h.assign(p->ws_visc_comp / sizeof(double), 0.0);
+        build_visc_tables(p, comp, beta, h.data());
+        if (hipMemcpyAsync(tab, h.data(), p->ws_visc_comp, hipMemcpyHostToDevice, S(p)) != hipSuccess)
+            return FSEI_ERR_HIP;
+        p->visc_beta[comp] = beta;
+    }
+    ViscArgs a{};
+    a.data = q;
+    // x: contiguous lines
+    a.tab = tab;
+    a.n = p->nx;
+    a.cyc = p->bcx == FSEI_BC_PERIODIC;
+    a.nlines = (long)p->ny * p->nz;
+    a.vec = (p->nx % 2 == 0 && aligned16(q)) ? 1 : 0;
+    {
+        Timed t(p, K_VISC_X);
+        launch_visc_x(p, a, p->visc_L[0]);
+    }
+    // y: lines of stride nx inside each z-plane
+    a.tab = tab + visc_tab_elems(p->visc_L[0]);
+    a.n = p->ny;
+    a.cyc = p->bcy == FSEI_BC_PERIODIC;
+    a.ncol = p->nx;
+    a.rstride = (size_t)p->nx;
+    a.bstride = (size_t)p->nx * p->ny;
+    {
+        Timed t(p, K_VISC_Y);
+        launch_visc_strided(p, a, p->visc_L[1], (unsigned)p->nz);
+    }
+    // z: lines of stride nx*ny, one group per y row
+    a.tab = tab + visc_tab_elems(p->visc_L[0]) + visc_tab_elems(p->visc_L[1]);
+    a.n = p->nz;
+    a.cyc = 0;
+    a.rstride = (size_t)p->nx * p->ny;
+    a.bstride = (size_t)p->nx;
+    {
+        Timed t(p, K_VISC_Z);
+        launch_visc_strided(p, a, p->visc_L[2], (unsigned)p->ny);
+    }
     return check_hip();
 }
 

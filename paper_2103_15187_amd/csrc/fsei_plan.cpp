@@ -74,6 +74,16 @@ void compute_layout(fsei_plan_impl* p) {
     p->ws_list = off;
     p->ws_list_bytes = (size_t)p->nlist * sizeof(int);
     off = round_up(off + p->ws_list_bytes, kAlign);
+    // viscous line-solve tables (3 components x 3 directions)
+    p->visc_L[0] = visc_chunk(p->nx);
+    p->visc_L[1] = visc_chunk(p->ny);
+    p->visc_L[2] = visc_chunk(p->nz);
+    p->ws_visc = off;
+    p->ws_visc_comp = 0;
+    if (p->visc_L[0] && p->visc_L[1] && p->visc_L[2])
+        p->ws_visc_comp = round_up((size_t)(visc_tab_elems(p->visc_L[0]) + visc_tab_elems(p->visc_L[1]) +
+                                            visc_tab_elems(p->visc_L[2])) * sizeof(double), kAlign);
+    off = round_up(off + 3 * p->ws_visc_comp, kAlign);
     // field 1: the intermediate field (FP64; FP32 for FP32 plans); for
     // FP32_REFINE it keeps f = D u* / dt in FP64
     const size_t esz = (p->precision == FSEI_PREC_FP32) ? sizeof(float) : sizeof(double);
@@ -256,3 +266,187 @@ fsei_status fsei_plan_workspace_size(const fsei_plan* p, size_t* bytes) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Viscous line-solve tables (paper, Sec. 2.1 eq. NSdiscr0 and Sec. 3: the
+// Crank-Nicolson viscous operator, approximately factorised into one
+// tridiagonal matrix I - beta L_d per direction, Thomas' algorithm with a
+// Sherman-Morrison correction for periodic lines).
+//
+// L_d is the staggered three-point second difference of the component:
+// along its own axis the component lives on faces (walls: the stored wall
+// face is dead, the opposite wall face is zero); along the other axes at
+// cell centres (walls: no-slip through a mirrored ghost, a wall flux of
+// 2 q / spacing over the half cell).  z is stretched and walled.
+// ---------------------------------------------------------------------------
+namespace fsei {
+
+namespace {
+
+struct Tri {
+    std::vector<double> a, b, c;   // sub, diagonal, super of I - beta L
+    double corner_lo = 0.0;        // periodic: entry (0, n-1)
+    double corner_hi = 0.0;        // periodic: entry (n-1, 0)
+    bool cyc = false;
+    bool dead0 = false;            // row 0 is a dead wall face
+};
+
+Tri visc_matrix(const fsei_plan_impl* p, int comp, int dir, double beta) {
+    Tri m;
+    const bool own = comp == dir;
+    const int n = dir == 0 ? p->nx : dir == 1 ? p->ny : p->nz;
+    m.a.assign(n, 0.0);
+    m.b.assign(n, 1.0);
+    m.c.assign(n, 0.0);
+    if (dir < 2) {
+        const double d = dir == 0 ? p->dx : p->dy;
+        const int bc = dir == 0 ? p->bcx : p->bcy;
+        const double k2 = beta / (d * d);
+        for (int i = 0; i < n; ++i) {
+            m.a[i] = (i > 0) ? -k2 : 0.0;
+            m.c[i] = (i + 1 < n) ? -k2 : 0.0;
+            m.b[i] = 1.0 + 2.0 * k2;
+        }
+        if (bc == FSEI_BC_PERIODIC) {
+            m.cyc = true;
+            m.corner_lo = -k2;
+            m.corner_hi = -k2;
+        } else if (own) {
+            // face 0 is the wall (dead); the face beyond the last is the
+            // other wall, value 0: the last row just loses its coupling
+            m.dead0 = true;
+            m.b[0] = 1.0;
+            m.c[0] = 0.0;
+            if (n > 1) m.a[1] = 0.0;
+        } else {
+            // mirrored ghost at both walls
+            m.b[0] = 1.0 + 3.0 * k2;
+            m.b[n - 1] = 1.0 + 3.0 * k2;
+        }
+        return m;
+    }
+    const std::vector<double>& dz = p->dz;
+    const std::vector<double>& h = p->h;
+    if (own) {
+        // w on z faces: face 0 is the bottom wall (dead), face nz the top wall
+        m.dead0 = true;
+        for (int k = 1; k < n; ++k) {
+            const double lo = 1.0 / (dz[k - 1] * h[k]);
+            const double hi = 1.0 / (dz[k] * h[k]);
+            m.a[k] = (k - 1 >= 1) ? -beta * lo : 0.0;
+            m.c[k] = (k + 1 < n) ? -beta * hi : 0.0;
+            m.b[k] = 1.0 + beta * (lo + hi);
+        }
+        return m;
+    }
+    for (int k = 0; k < n; ++k) {
+        const double lo = (k >= 1) ? 1.0 / (h[k] * dz[k]) : 2.0 / (dz[0] * dz[0]);
+        const double hi = (k + 1 < n) ? 1.0 / (h[k + 1] * dz[k]) : 2.0 / (dz[k] * dz[k]);
+        m.a[k] = (k >= 1) ? -beta * lo : 0.0;
+        m.c[k] = (k + 1 < n) ? -beta * hi : 0.0;
+        m.b[k] = 1.0 + beta * (lo + hi);
+    }
+    return m;
+}
+
+// Thomas solve on the host (periodic Sherman-Morrison vector only)
+std::vector<double> host_thomas(const std::vector<double>& a, const std::vector<double>& b,
+                                const std::vector<double>& c, std::vector<double> f) {
+    const int n = (int)b.size();
+    std::vector<double> cp(n);
+    double piv = b[0];
+    cp[0] = c[0] / piv;
+    f[0] /= piv;
+    for (int i = 1; i < n; ++i) {
+        piv = b[i] - a[i] * cp[i - 1];
+        cp[i] = c[i] / piv;
+        f[i] = (f[i] - a[i] * f[i - 1]) / piv;
+    }
+    for (int i = n - 2; i >= 0; --i) f[i] -= cp[i] * f[i + 1];
+    return f;
+}
+
+void visc_block(const Tri& m0, int L, double* out) {
+    const int n = (int)m0.b.size();
+    const int NP = kViscPmax * L;
+    double* rr = out;
+    double* al = out + NP;
+    double* wr = out + 2 * NP;
+    double* cn = out + 3 * NP;
+    double* vr = out + 4 * NP;
+    double* zt = out + 5 * NP;
+    double* wl = out + 6 * NP;
+    double* vl = wl + kViscLv * kViscPmax;
+    std::fill(out, out + visc_tab_elems(L), 0.0);
+    Tri m = m0;
+    double vq = 0.0;
+    if (m.cyc) {
+        // A = A' + u v^T with u = (g, 0, .., corner_hi), v = (1, 0, .., corner_lo / g)
+        const double g = -m.b[0];
+        m.b[0] -= g;
+        m.b[n - 1] -= m.corner_lo * m.corner_hi / g;
+        vq = m.corner_lo / g;
+        std::vector<double> u(n, 0.0);
+        u[0] = g;
+        u[n - 1] += m.corner_hi;
+        const std::vector<double> z = host_thomas(m.a, m.b, m.c, u);
+        const double den = 1.0 + z[0] + vq * z[n - 1];
+        for (int t = 0; t < n; ++t) zt[t] = z[t] / den;
+    }
+    // Thomas factorisation of the (modified) tridiagonal matrix: pivots,
+    // then the coefficients of the two substitution recurrences
+    std::vector<double> pv(n);
+    pv[0] = m.b[0];
+    for (int t = 1; t < n; ++t) pv[t] = m.b[t] - m.a[t] * m.c[t - 1] / pv[t - 1];
+    for (int t = 0; t < n; ++t) {
+        rr[t] = (t == 0 && m.dead0) ? 0.0 : 1.0 / pv[t];
+        al[t] = (t == 0) ? 0.0 : -m.a[t] * rr[t];
+        cn[t] = -m.c[t] * rr[t];
+    }
+    // per-row carry products inside each chunk
+    for (int q = 0; q < kViscPmax; ++q) {
+        double pr = 1.0;
+        for (int t = q * L; t < (q + 1) * L; ++t) {
+            pr *= al[t];
+            wr[t] = pr;
+        }
+        pr = 1.0;
+        for (int t = (q + 1) * L - 1; t >= q * L; --t) {
+            pr *= cn[t];
+            vr[t] = pr;
+        }
+    }
+    // Kogge-Stone multipliers over the chunks
+    double W[kViscPmax], Vv[kViscPmax];
+    for (int q = 0; q < kViscPmax; ++q) {
+        W[q] = wr[q * L + L - 1];
+        Vv[q] = vr[q * L];
+    }
+    for (int lv = 0; lv < kViscLv; ++lv) {
+        const int s = 1 << lv;
+        double Wn[kViscPmax], Vn[kViscPmax];
+        for (int q = 0; q < kViscPmax; ++q) {
+            wl[lv * kViscPmax + q] = W[q];
+            vl[lv * kViscPmax + q] = Vv[q];
+            Wn[q] = (q >= s) ? W[q] * W[q - s] : W[q];
+            Vn[q] = (q + s < kViscPmax) ? Vv[q] * Vv[q + s] : Vv[q];
+        }
+        for (int q = 0; q < kViscPmax; ++q) {
+            W[q] = Wn[q];
+            Vv[q] = Vn[q];
+        }
+    }
+    vl[kViscLv * kViscPmax] = vq;
+}
+
+}  // namespace
+
+void build_visc_tables(const fsei_plan_impl* p, int comp, double beta, double* out) {
+    for (int d = 0; d < 3; ++d) {
+        const int L = p->visc_L[d];
+        visc_block(visc_matrix(p, comp, d, beta), L, out);
+        out += visc_tab_elems(L);
+    }
+}
+
+}  // namespace fsei

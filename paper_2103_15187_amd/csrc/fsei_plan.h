@@ -34,6 +34,25 @@ constexpr int tile_nseq(int emax, int N, int ps = kPadShift) {
 }
 inline int x_nseq(int nx) { return tile_nseq(x_emax(nx), nx) > 0 ? tile_nseq(x_emax(nx), nx) : 1; }
 
+// Line solves of the implicit viscous step: every line is cut into
+// kViscPmax chunks of L rows (L one of the compiled sizes), so lines of up
+// to kViscPmax * 32 rows are supported.  One table block per (component,
+// direction) holds visc_tab_elems(L) doubles (layout in fsei_viscous.h).
+constexpr int kViscPmax = 32;
+constexpr int kViscLv = 5;   // Kogge-Stone levels over the chunks, log2(kViscPmax)
+constexpr int kViscMaxN = kViscPmax * 32;
+constexpr int visc_tab_elems(int L) { return 6 * kViscPmax * L + 2 * kViscLv * kViscPmax + 2; }
+// chunk length for a line of n rows (0: too long)
+constexpr int visc_chunk(int n) {
+    return n <= kViscPmax * 4    ? 4
+           : n <= kViscPmax * 8  ? 8
+           : n <= kViscPmax * 12 ? 12
+           : n <= kViscPmax * 16 ? 16
+           : n <= kViscPmax * 24 ? 24
+           : n <= kViscPmax * 32 ? 32
+                                 : 0;
+}
+
 // Radix schedule of one complex FFT length (radices 8, 4, 2, 3).
 struct FftPlan {
     int n = 0;
@@ -99,6 +118,14 @@ struct fsei_plan_impl {
     size_t ws_field3 = 0, ws_field3_bytes = 0;     // refine: FP64 pressure when the caller passes none
     size_t ws_field4 = 0, ws_field4_bytes = 0;     // refine: FP32 pressure of the first solve
     size_t ws_list = 0, ws_list_bytes = 0;         // mode lines solved in FP64 by FP32 plans
+    // implicit viscous step: chunk length per direction (x, y, z; 0 when a
+    // line is longer than kViscMaxN), the table blocks of the three
+    // components (x, y, z blocks each), and the beta each component's
+    // tables were last built for (NaN: not built for this workspace)
+    int visc_L[3] = {0, 0, 0};
+    size_t ws_visc = 0, ws_visc_comp = 0;           // region offset, bytes per component
+    double visc_beta[3] = {0, 0, 0};
+    std::vector<double> visc_host[3];
     size_t ws_total = 0;
     size_t n_partials = 0;                          // per-block partial sums (triples)
     static constexpr int kScalars = 64;
@@ -127,6 +154,9 @@ struct fsei_plan_impl {
 // Host-side helpers (fsei_plan.cpp).
 bool factor_radices(int n, FftPlan* out);
 void compute_layout(fsei_plan_impl* p);
+// Tables of the viscous line solves of component comp (0 u, 1 v, 2 w) for
+// beta, x, y and z blocks one after the other (ws_visc_comp bytes).
+void build_visc_tables(const fsei_plan_impl* p, int comp, double beta, double* out);
 
 }  // namespace fsei
 

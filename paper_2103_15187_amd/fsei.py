@@ -8,7 +8,8 @@ is no fallback implementation.
 
 Functions follow the C ABI in ``include/fsei.h``:
 ``fsei_poisson_plan_create`` / ``fsei_poisson_solve`` / ``fsei_project`` /
-``fsei_project_backward`` (+ FP32 variants).  ``ProjectFn`` wraps the forward
+``fsei_project_backward`` (+ FP32 variants), and ``fsei_viscous_solve`` (the
+implicit viscous step).  ``ProjectFn`` wraps the forward
 projection and its hand-written adjoint as a ``torch.autograd.Function``.
 """
 from __future__ import annotations
@@ -24,6 +25,7 @@ WALL = 1
 PREC_FP64 = 0
 PREC_FP32_REFINE = 1
 PREC_FP32 = 2
+NUM_KERNEL_SLOTS = 20   # FSEI_NUM_KERNEL_SLOTS
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsei.so")
@@ -69,6 +71,7 @@ def lib():
         "fsei_project_backward": (I, [P, P, P, P, P, D]),
         "fsei_project_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_project_backward_f32": (I, [P, P, P, P, P, ctypes.c_float]),
+        "fsei_viscous_solve": (I, [P, I, P, D]),
         "fsei_plan_set_timing": (I, [P, I]),
         "fsei_plan_reset_timing": (I, [P]),
         "fsei_plan_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long),
@@ -224,6 +227,21 @@ class Plan:
             _check(lib().fsei_project_backward(self._h, _ptr(gu), _ptr(gv), _ptr(gw), _ptr(gp), float(dt)),
                    "fsei_project_backward")
 
+    def viscous_solve(self, q, component, beta):
+        """In place: q <- dq with (I - beta Lx)(I - beta Ly)(I - beta Lz) dq = q
+        for velocity component 0 (u), 1 (v) or 2 (w) (implicit viscous step)."""
+        import torch
+        q = self._field(q, torch.float64, "q")
+        self._stream()
+        _check(lib().fsei_viscous_solve(self._h, int(component), _ptr(q), float(beta)), "fsei_viscous_solve")
+        return q
+
+    def viscous_step(self, u, v, w, beta):
+        """viscous_solve of the three components, each in place."""
+        for c, q in enumerate((u, v, w)):
+            self.viscous_solve(q, c, beta)
+        return u, v, w
+
     # -- measurement ----------------------------------------------------------
     def set_timing(self, enable=True):
         _check(lib().fsei_plan_set_timing(self._h, 1 if enable else 0), "fsei_plan_set_timing")
@@ -234,7 +252,7 @@ class Plan:
     def kernel_times(self):
         """{kernel name: (total ms, launches)} for kernels launched while timing was on."""
         out = {}
-        for slot in range(16):
+        for slot in range(NUM_KERNEL_SLOTS):
             ms = ctypes.c_double()
             n = ctypes.c_long()
             name = ctypes.c_char_p()

@@ -91,6 +91,7 @@ def test_plan_lifecycle_and_workspace_size_host_only():
     assert L.fsei_project(h, d, d, d, d, 1.0, None) == ERR_WORKSPACE
     assert L.fsei_poisson_solve(h, d, d, None) == ERR_WORKSPACE
     assert L.fsei_project_backward(h, d, d, d, None, 1.0) == ERR_WORKSPACE
+    assert L.fsei_viscous_solve(h, 0, d, 1e-3) == ERR_WORKSPACE
     L.fsei_poisson_plan_destroy(h)
     L.fsei_poisson_plan_destroy(None)
 
@@ -100,3 +101,4 @@ def test_null_arguments():
     assert L.fsei_poisson_plan_create(8, 8, 8, None, 0.1, 0.1, None, None) == ERR_ARG
     assert L.fsei_plan_workspace_size(None, None) == ERR_ARG
     assert L.fsei_project(None, None, None, None, None, 1.0, None) == ERR_ARG
+    assert L.fsei_viscous_solve(None, 0, None, 1.0) == ERR_ARG
