@@ -279,32 +279,61 @@ __global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided(ViscArgs a) {
 template <int L>
 __global__ __launch_bounds__(kViscXLines * kViscPmax) void k_visc_x(ViscArgs a) {
     constexpr int TXL = kViscXLines, NT = TXL * kViscPmax;
+    constexpr int IPL = (16 * L + NT - 1) / NT;   // 16-byte loads per line and thread (n <= 32 L)
     __shared__ double st[visc_tab_elems(L)];
     __shared__ double sc[2 * NT];
     __shared__ double sx[2 * TXL];
     extern __shared__ __align__(16) unsigned char visc_dyn[];
     double* tile = reinterpret_cast<double*>(visc_dyn);
     visc_load_tables<L, NT>(a.tab, st);
-    const int n = a.n, sp = n + 2;
-    const bool even = a.vec != 0;
+    const int n = a.n, sp = n + 2, h2 = n / 2;
+    const bool vec = a.vec != 0;   // uniform
     const int ln = threadIdx.x % TXL, p = threadIdx.x / TXL;
     const int s0 = p * L;
-    for (int tt = 0; tt < kViscXTiles; ++tt) {
-        const long line0 = ((long)blockIdx.x * kViscXTiles + tt) * TXL;
+    // 16-byte path: the next tile's loads are issued into registers before
+    // the current tile is solved, so they are in flight during the solve
+    // (indices clamped into the tile, so every lane loads unconditionally;
+    // the clamped values are never stored)
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    d2 pre[TXL][IPL];
+#define FSEI_VISC_FETCH(L0, NL)                                                                        \
+    {                                                                                                  \
+        const double* __restrict__ gf = a.data + (size_t)(L0) * n;                                     \
+        _Pragma("unroll") for (int l = 0; l < TXL; ++l) _Pragma("unroll") for (int r = 0; r < IPL; ++r) { \
+            const int lc = (l < (NL)) ? l : (NL) - 1;                                                  \
+            int i2 = threadIdx.x + r * NT;                                                             \
+            i2 = (i2 < h2) ? i2 : h2 - 1;                                                              \
+            pre[l][r] = *reinterpret_cast<const d2*>(gf + (size_t)lc * n + 2 * i2);                    \
+        }                                                                                              \
+    }
+    long line0 = (long)blockIdx.x * kViscXTiles * TXL;
+    if (vec && line0 < a.nlines) FSEI_VISC_FETCH(line0, ((a.nlines - line0 < TXL) ? (int)(a.nlines - line0) : TXL))
+    // unrolled: the prefetch registers then stay registers across tiles
+#pragma unroll
+    for (int tt = 0; tt < kViscXTiles; ++tt, line0 += TXL) {
         if (line0 >= a.nlines) break;   // uniform over the workgroup
         const int nl = (a.nlines - line0 < TXL) ? (int)(a.nlines - line0) : TXL;
         double* __restrict__ g = a.data + (size_t)line0 * n;
         __syncthreads();   // the previous tile's stores have read the tile
-        for (int l = 0; l < nl; ++l) {
-            if (even) {
-                for (int i = 2 * threadIdx.x; i < n; i += 2 * NT)
-                    *reinterpret_cast<double2*>(tile + l * sp + i) =
-                        *reinterpret_cast<const double2*>(g + (size_t)l * n + i);
-            } else {
+        if (vec) {
+            // every register goes to its (clamped) slot: rows past nl are
+            // never read back, a clamped column rewrites its own value
+#pragma unroll
+            for (int l = 0; l < TXL; ++l)
+#pragma unroll
+                for (int r = 0; r < IPL; ++r) {
+                    int i2 = threadIdx.x + r * NT;
+                    i2 = (i2 < h2) ? i2 : h2 - 1;
+                    *reinterpret_cast<d2*>(tile + l * sp + 2 * i2) = pre[l][r];
+                }
+        } else {
+            for (int l = 0; l < nl; ++l)
                 for (int i = threadIdx.x; i < n; i += NT) tile[l * sp + i] = g[(size_t)l * n + i];
-            }
         }
         __syncthreads();   // tile (and, first time, tables) staged
+        const long next = line0 + TXL;
+        if (vec && tt + 1 < kViscXTiles && next < a.nlines)
+            FSEI_VISC_FETCH(next, ((a.nlines - next < TXL) ? (int)(a.nlines - next) : TXL))
         double F[1][L];
 #pragma unroll
         for (int t = 0; t < L; ++t) F[0][t] = (s0 + t < n && ln < nl) ? tile[ln * sp + s0 + t] : 0.0;
@@ -315,8 +344,9 @@ __global__ __launch_bounds__(kViscXLines * kViscPmax) void k_visc_x(ViscArgs a) 
                 if (s0 + t < n) tile[ln * sp + s0 + t] = F[0][t];
         }
         __syncthreads();
+#undef FSEI_VISC_FETCH
         for (int l = 0; l < nl; ++l) {
-            if (even) {
+            if (vec) {
                 for (int i = 2 * threadIdx.x; i < n; i += 2 * NT)
                     *reinterpret_cast<double2*>(g + (size_t)l * n + i) =
                         *reinterpret_cast<const double2*>(tile + l * sp + i);
