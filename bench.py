@@ -220,7 +220,8 @@ def summarize_profiles(d, cmd_trace, cmd_pmc):
     import csv
     out = os.path.join(ROOT, "profiles")
     rows = list(csv.DictReader(open(os.path.join(d, "prof", "c3_kernel_stats.csv"))))
-    md = ["# Kernel trace: projection, 512x512x768 walls tanh 2.5 (FP32+refine and FP64 modes)", "",
+    md = ["# Kernel trace: projection (FP32+refine and FP64 modes) and implicit viscous step, "
+          "512x512x768 walls tanh 2.5", "",
           "Command (run from the repository root on one MI355X):", "", "```", cmd_trace, "```", "",
           "| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
     for r in rows:
@@ -255,7 +256,7 @@ def summarize_profiles(d, cmd_trace, cmd_pmc):
            "kernels": kern}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(res, fh, indent=1, sort_keys=True)
-    md = ["# HBM traffic per kernel launch: projection, 512x512x768 walls tanh 2.5", "",
+    md = ["# HBM traffic per kernel launch: projection and implicit viscous step, 512x512x768 walls tanh 2.5", "",
           "Commands (run from the repository root on one MI355X; one counter per run):", "", "```", cmd_pmc, "```", "",
           f"Counters scaled by the reading of a plain streaming kernel of known size (torch.neg over one FP64 "
           f"field, 8 B read + 8 B written per cell): FETCH_SIZE x{cal['FETCH_SIZE']:.3f}, "
