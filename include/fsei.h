@@ -174,6 +174,27 @@ fsei_status fsei_project_backward_f32(fsei_plan* plan, float* gu, float* gv, flo
  * new tables; otherwise the call only enqueues three kernels. */
 fsei_status fsei_viscous_solve(fsei_plan* plan, int component, double* q, double beta);
 
+/* Explicit right-hand side of the momentum step (paper, Sec. 2.1, eq.
+ * NSdiscr0: Adams-Bashforth for the convective term with weights gamma, rho
+ * (3/2, -1/2; 1, 0 for a first step), Crank-Nicolson for the viscous term;
+ * the pressure is left to the projection).  Computes, per component,
+ *
+ *     rhs = dt [ -(gamma N^n + rho N^{n-1}) + (1/Re) Lap u^n ],   N = div(u u),
+ *
+ * the right-hand side of the implicit viscous step (fsei_viscous_solve), and
+ * N^n for the next step.  N is the divergence form on each component's
+ * control volume (two-point means in x and y, linear interpolation in the
+ * stretched z, no flux through walls); Lap is the operator of
+ * fsei_viscous_solve.  Dead wall faces are ignored on input and written 0.
+ *   u, v, w    : device, u^n (read only)
+ *   nu, nv, nw : device, in: N^{n-1} (not read when rho == 0), out: N^n
+ *   ru, rv, rw : device, out: rhs; must not alias u, v, w, nu, nv, nw
+ *   dt, re     : > 0, finite;  gamma, rho: finite
+ * All fields (nz, ny, nx) FP64.  Needs the plan's workspace (z metrics). */
+fsei_status fsei_momentum_rhs(fsei_plan* plan, const double* u, const double* v, const double* w, double* nu,
+                              double* nv, double* nw, double* ru, double* rv, double* rw, double dt, double re,
+                              double gamma, double rho);
+
 /* Per-kernel timing with HIP events on the plan's stream (for measurement).
  * enable != 0 records an event pair around every launch from now on;
  * fsei_plan_reset_timing clears the accumulators. */

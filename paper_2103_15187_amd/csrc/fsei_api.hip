@@ -12,6 +12,7 @@
 #include "fsei_kernels.h"
 #include "fsei_plan.h"
 #include "fsei_viscous.h"
+#include "fsei_momentum.h"
 
 using namespace fsei;
 using namespace fsei::dev;
@@ -22,7 +23,7 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "", ""};
+    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "momentum_rhs", ""};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
 constexpr int K_RESID_PAIRS = 12;
@@ -31,6 +32,7 @@ constexpr int K_GRAD_RESID = 14;
 constexpr int K_VISC_X = 15;
 constexpr int K_VISC_Y = 16;
 constexpr int K_VISC_Z = 17;
+constexpr int K_MOM_RHS = 18;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -1153,6 +1155,49 @@ fsei_status fsei_viscous_solve(fsei_plan* p, int comp, double* q, double beta) {
     {
         Timed t(p, K_VISC_Z);
         launch_visc_strided(p, a, p->visc_L[2], (unsigned)p->ny);
+    }
+    return check_hip();
+}
+
+fsei_status fsei_momentum_rhs(fsei_plan* p, const double* u, const double* v, const double* w, double* nu,
+                              double* nv, double* nw, double* ru, double* rv, double* rw, double dt, double re,
+                              double gamma, double rho) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!u || !v || !w || !nu || !nv || !nw || !ru || !rv || !rw) return FSEI_ERR_ARG;
+    if (!good_dt(dt) || !std::isfinite(re) || !(re > 0.0) || !std::isfinite(gamma) || !std::isfinite(rho))
+        return FSEI_ERR_ARG;
+    MomArgs a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.perx = p->bcx == FSEI_BC_PERIODIC;
+    a.pery = p->bcy == FSEI_BC_PERIODIC;
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.nu = nu;
+    a.nv = nv;
+    a.nw = nw;
+    a.ru = ru;
+    a.rv = rv;
+    a.rw = rw;
+    a.idx = 1.0 / p->dx;
+    a.idy = 1.0 / p->dy;
+    a.idx2 = a.idx * a.idx;
+    a.idy2 = a.idy * a.idy;
+    a.dt = dt;
+    a.inv_re = 1.0 / re;
+    a.gamma = gamma;
+    a.rho = rho;
+    a.dz = tab<double>(p, T_DZ);
+    a.inv_dz = tab<double>(p, T_INV_DZ);
+    a.inv_h = tab<double>(p, T_INV_H);
+    a.za = tab<double>(p, T_ZA);
+    a.zc = tab<double>(p, T_ZC);
+    {
+        Timed t(p, K_MOM_RHS);
+        hipLaunchKernelGGL((k_momentum_rhs<256>), dim3((unsigned)p->ny, (unsigned)p->nz), dim3(256), 0, S(p), a);
     }
     return check_hip();
 }

@@ -72,6 +72,7 @@ def lib():
         "fsei_project_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_project_backward_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_viscous_solve": (I, [P, I, P, D]),
+        "fsei_momentum_rhs": (I, [P, P, P, P, P, P, P, P, P, P, D, D, D, D]),
         "fsei_plan_set_timing": (I, [P, I]),
         "fsei_plan_reset_timing": (I, [P]),
         "fsei_plan_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long),
@@ -235,6 +236,19 @@ class Plan:
         self._stream()
         _check(lib().fsei_viscous_solve(self._h, int(component), _ptr(q), float(beta)), "fsei_viscous_solve")
         return q
+
+    def momentum_rhs(self, u, v, w, n, r, dt, re, gamma=1.5, rho=-0.5):
+        """r <- dt [-(gamma N^n + rho N^{n-1}) + Lap u^n / Re] per component and
+        n <- N^n (n holds N^{n-1} on entry; r, n: 3-tuples of fields)."""
+        import torch
+        u, v, w = (self._field(a, torch.float64, nm) for a, nm in ((u, "u"), (v, "v"), (w, "w")))
+        n = [self._field(a, torch.float64, "n") for a in n]
+        r = [self._field(a, torch.float64, "r") for a in r]
+        self._stream()
+        _check(lib().fsei_momentum_rhs(self._h, _ptr(u), _ptr(v), _ptr(w), *(_ptr(a) for a in n),
+                                       *(_ptr(a) for a in r), float(dt), float(re), float(gamma), float(rho)),
+               "fsei_momentum_rhs")
+        return r
 
     def viscous_step(self, u, v, w, beta):
         """viscous_solve of the three components, each in place."""
