@@ -45,6 +45,7 @@ SLOT_KERNEL = {
                     "grad_resid": "k_grad_resid<256, 16, false>"},
     "viscous_fp64": {"visc_x": "k_visc_x<16>", "visc_y": "k_visc_strided<2, 16>",
                      "visc_z": "k_visc_strided<2, 24>"},
+    "momentum_fp64": {"momentum_rhs": "k_momentum_rhs<256>"},
 }
 
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:
@@ -59,6 +60,8 @@ BYTES_PER_CELL = {
     # implicit viscous step: every line solve of one component reads and
     # writes the field once (3 components x 3 directions = 144 B/cell)
     "viscous_fp64": {"visc_x": 16, "visc_y": 16, "visc_z": 16},
+    # explicit momentum right-hand side: u, v, w and N^{n-1} read, rhs and N^n written
+    "momentum_fp64": {"momentum_rhs": 96},
 }
 
 
@@ -140,6 +143,35 @@ def gpu_viscous(spec, u0, v0, w0, steps, warmup, torch, fsei):
     res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": plan.kernel_times(), "kernel_steps": nk,
            "last_info": None, "div_check": None, "beta": beta}
     del u, v, w
+    torch.cuda.empty_cache()
+    return res
+
+
+def gpu_momentum(spec, u0, v0, w0, steps, warmup, torch, fsei):
+    """Time `steps` explicit momentum right-hand sides (fsei_momentum_rhs) on
+    resident fields (N^{n-1} taken from the previous call)."""
+    plan = fsei.Plan.from_spec(spec)
+    n = [torch.zeros_like(u0) for _ in range(3)]
+    r = [torch.empty_like(u0) for _ in range(3)]
+    dt, re = 1e-3, 1000.0
+    for _ in range(warmup):
+        plan.momentum_rhs(u0, v0, w0, n, r, dt, re)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.momentum_rhs(u0, v0, w0, n, r, dt, re)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nk = min(steps, 3)
+    plan.reset_timing()
+    plan.set_timing(True)
+    for _ in range(nk):
+        plan.momentum_rhs(u0, v0, w0, n, r, dt, re)
+    torch.cuda.synchronize()
+    plan.set_timing(False)
+    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": plan.kernel_times(), "kernel_steps": nk,
+           "last_info": None, "div_check": None}
+    del n, r
     torch.cuda.empty_cache()
     return res
 
@@ -362,7 +394,8 @@ def main():
     ap.add_argument("--modes", default="fp32_refine,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-viscous", action="store_true",
-                    help="skip the implicit viscous step (reported beside the projection, not in value)")
+                    help="skip the implicit viscous step and the momentum right-hand side (reported beside the "
+                         "projection, not in value)")
     ap.add_argument("--calib", action="store_true",
                     help="also run torch.neg over one field (a plain streaming kernel of known size: "
                          "reads and writes 8 B per cell) to calibrate hardware byte counters")
@@ -448,6 +481,14 @@ def main():
         if not args.no_cpu_baseline:
             vs["cpu_baseline"] = cpu_baseline_viscous(spec, vres["beta"])
         line["modes"]["viscous_fp64"] = vs
+        log(f"[bench] momentum right-hand side: warmup {args.warmup}, steps {args.steps}")
+        mres = gpu_momentum(spec, u0, v0, w0, args.steps, args.warmup, torch, fsei)
+        log(f"[bench] momentum right-hand side: {mres['ms_per_step']:.3f} ms/step")
+        ms = mode_summary("momentum_fp64", mres, ncells)
+        ms.pop("max_abs_div_after", None)
+        ms["steps_per_s"] = ms.pop("solves_per_s")
+        ms["roofline"] = roofline_for("momentum_fp64", mres, ncells)
+        line["modes"]["momentum_fp64"] = ms
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(spec)

@@ -1197,7 +1197,11 @@ fsei_status fsei_momentum_rhs(fsei_plan* p, const double* u, const double* v, co
     a.zc = tab<double>(p, T_ZC);
     {
         Timed t(p, K_MOM_RHS);
-        hipLaunchKernelGGL((k_momentum_rhs<256>), dim3((unsigned)p->ny, (unsigned)p->nz), dim3(256), 0, S(p), a);
+        const unsigned nb = (unsigned)((long)p->ny * p->nz);
+        if (p->ny % 16 == 0)
+            hipLaunchKernelGGL((k_momentum_rhs<256, 16>), dim3(nb), dim3(256), 0, S(p), a);
+        else
+            hipLaunchKernelGGL((k_momentum_rhs<256, 1>), dim3(nb), dim3(256), 0, S(p), a);
     }
     return check_hip();
 }

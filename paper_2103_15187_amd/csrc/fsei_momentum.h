@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "fsei_plan.h"
+#include "fsei_transforms.h"   // xcd_remap
 
 namespace fsei {
 namespace dev {
@@ -42,11 +43,19 @@ struct MomArgs {
     const double* zc;       // 1/(dz_k h_{k+1}), k <= nz-2
 };
 
-// One workgroup per (j, k) row; lanes over x.
-template <int NT>
+// One workgroup per (j, k) row; lanes over x.  Rows are visited in tiles
+// of GJ rows, plane by plane inside a tile, each XCD taking a contiguous run
+// of rows: the j +- 1 and k +- 1 rows a workgroup reads were just read by its
+// neighbours on the same XCD (L2 hits rather than HBM re-reads).
+template <int NT, int GJ>
 __global__ __launch_bounds__(NT) void k_momentum_rhs(MomArgs a) {
-    const int j = blockIdx.x, k = blockIdx.y;
     const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int per = nz * GJ;
+    const int jt = b / per;
+    const int rem = b - jt * per;
+    const int k = rem / GJ;
+    const int j = jt * GJ + (rem - k * GJ);
     const size_t nxy = (size_t)nx * ny;
     const bool wx = !a.perx, wy = !a.pery;
     // field value with the grid's boundary conventions: outside the grid 0
