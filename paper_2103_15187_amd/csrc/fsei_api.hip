@@ -1198,7 +1198,15 @@ fsei_status fsei_momentum_rhs(fsei_plan* p, const double* u, const double* v, co
     {
         Timed t(p, K_MOM_RHS);
         const unsigned nb = (unsigned)((long)p->ny * p->nz);
-        if (p->ny % 16 == 0)
+        // cell pairs as 16-byte accesses when the rows allow
+        const bool pairs = p->nx % 2 == 0 && aligned16(u) && aligned16(v) && aligned16(w) && aligned16(nu) &&
+                           aligned16(nv) && aligned16(nw) && aligned16(ru) && aligned16(rv) && aligned16(rw);
+        const bool t16 = p->ny % 16 == 0;
+        if (pairs && t16)
+            hipLaunchKernelGGL((k_momentum_rhs_pairs<256, 16>), dim3(nb), dim3(256), 0, S(p), a);
+        else if (pairs)
+            hipLaunchKernelGGL((k_momentum_rhs_pairs<256, 1>), dim3(nb), dim3(256), 0, S(p), a);
+        else if (t16)
             hipLaunchKernelGGL((k_momentum_rhs<256, 16>), dim3(nb), dim3(256), 0, S(p), a);
         else
             hipLaunchKernelGGL((k_momentum_rhs<256, 1>), dim3(nb), dim3(256), 0, S(p), a);
