@@ -176,6 +176,49 @@ def gpu_momentum(spec, u0, v0, w0, steps, warmup, torch, fsei):
     return res
 
 
+def gpu_ib(spec, u0, steps, warmup, torch, fsei, nb=1_000_000):
+    """Time `steps` IB-MLS transfers of nb markers (interpolation of the three
+    velocity components at the markers, then spreading of one value per
+    marker and component back to the grid).  Markers: uniform in the domain."""
+    import numpy as np
+    from paper_2103_15187_amd import workloads as W
+    plan = fsei.Plan.from_spec(spec)
+    r = W.rng(123)
+    zc = spec.zc()
+    xb = np.stack([r.uniform(0, spec.lx, nb), r.uniform(0, spec.ly, nb), r.uniform(zc[0], zc[-1], nb)], 1)
+    xd = torch.from_numpy(xb).to(u0.device)
+    fb = torch.ones(nb, dtype=torch.float64, device=u0.device)
+    dvb = torch.full((nb,), spec.dx * spec.dy * 1e-3, dtype=torch.float64, device=u0.device)
+    ub = torch.empty(nb, dtype=torch.float64, device=u0.device)
+    f = torch.zeros_like(u0)
+
+    def step():
+        for c in range(3):
+            plan.ib_interpolate(u0, c, xd, ub)
+            plan.ib_spread(f, c, xd, fb, dvb)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.reset_timing()
+    plan.set_timing(True)
+    step()
+    torch.cuda.synchronize()
+    plan.set_timing(False)
+    kt = plan.kernel_times()
+    ms = (t1 - t0) * 1e3 / steps
+    del f, xd, fb, dvb, ub
+    torch.cuda.empty_cache()
+    return {"ms_per_step": round(ms, 4), "markers": nb, "markers_per_s": round(nb / (ms / 1e3), 1),
+            "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()},
+            "note": "one step = interpolation of u, v, w at every marker + spreading of one value per marker "
+                    "and component (27-node MLS supports, FP64 atomics); markers uniform in the 512x512x768 domain"}
+
+
 def divergence_max(u, v, w, spec, torch):
     """max |D u| of the projected field, relative to max |D u*| scale 1 (GPU,
     torch ops; a property check, not part of the timed path)."""
@@ -394,8 +437,8 @@ def main():
     ap.add_argument("--modes", default="fp32_refine,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-viscous", action="store_true",
-                    help="skip the implicit viscous step and the momentum right-hand side (reported beside the "
-                         "projection, not in value)")
+                    help="skip the implicit viscous step, the momentum right-hand side and the IB-MLS transfer "
+                         "(reported beside the projection, not in value)")
     ap.add_argument("--calib", action="store_true",
                     help="also run torch.neg over one field (a plain streaming kernel of known size: "
                          "reads and writes 8 B per cell) to calibrate hardware byte counters")
@@ -489,6 +532,9 @@ def main():
         ms["steps_per_s"] = ms.pop("solves_per_s")
         ms["roofline"] = roofline_for("momentum_fp64", mres, ncells)
         line["modes"]["momentum_fp64"] = ms
+        log("[bench] IB-MLS transfer of 10^6 markers")
+        line["modes"]["ib_mls_fp64"] = gpu_ib(spec, u0, args.steps, args.warmup, torch, fsei)
+        log(f"[bench] IB-MLS: {line['modes']['ib_mls_fp64']['ms_per_step']:.3f} ms/step")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(spec)

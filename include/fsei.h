@@ -195,6 +195,30 @@ fsei_status fsei_momentum_rhs(fsei_plan* plan, const double* u, const double* v,
                               double* nv, double* nw, double* ru, double* rv, double* rw, double dt, double re,
                               double gamma, double rho);
 
+/* Immersed-boundary moving-least-squares transfer between nb Lagrangian
+ * markers and one velocity component (paper, Sec. 2.1, eq. interpv, Fig.
+ * mls).  Each marker's support is the 3 x 3 x 3 nodes of the component's own
+ * staggered lattice around the node nearest to it (shifted inwards at walls,
+ * wrapped across periodic boundaries); the transfer operators are
+ * moving-least-squares on the linear basis [1, x, y, z] with the weight
+ * exp(-(dx/Dx)^2 - (dy/Dy)^2 - (dz/Hz)^2), Hz the z extent of the middle
+ * node's control volume.  They reproduce linear fields exactly.
+ *   comp  : 0 (u), 1 (v), 2 (w)
+ *   xb    : device, (nb, 3) marker positions x, y, z (any value gives an
+ *           in-grid support; positions outside the domain get the nearest one)
+ * fsei_ib_interpolate: ub[b] = sum_k phi_k(x_b) field[k]
+ *   field : device (nz, ny, nx) FP64, read;  ub: device (nb) FP64, written
+ * fsei_ib_spread: field[k] += sum_b phi_k(x_b) fb[b] dvb[b] / V_k, V_k the
+ *   node's control volume (dx dy dz_k; dx dy h_k for w): the volume-weighted
+ *   transpose of interpolation.  Atomic FP64 additions, so the summation
+ *   order (and the last bits) may differ from call to call.
+ *   field : device, accumulated;  fb, dvb: device (nb) marker values, volumes
+ * nb >= 0 (0: nothing to do); nx, ny, nz >= 3 (FSEI_ERR_SIZE otherwise). */
+fsei_status fsei_ib_interpolate(fsei_plan* plan, int comp, const double* field, const double* xb, long nb,
+                                double* ub);
+fsei_status fsei_ib_spread(fsei_plan* plan, int comp, double* field, const double* xb, const double* fb,
+                           const double* dvb, long nb);
+
 /* Per-kernel timing with HIP events on the plan's stream (for measurement).
  * enable != 0 records an event pair around every launch from now on;
  * fsei_plan_reset_timing clears the accumulators. */

@@ -13,6 +13,7 @@
 #include "fsei_plan.h"
 #include "fsei_viscous.h"
 #include "fsei_momentum.h"
+#include "fsei_ibm.h"
 
 using namespace fsei;
 using namespace fsei::dev;
@@ -23,7 +24,7 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "momentum_rhs", ""};
+    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "momentum_rhs", "ib_transfer"};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
 constexpr int K_RESID_PAIRS = 12;
@@ -33,6 +34,7 @@ constexpr int K_VISC_X = 15;
 constexpr int K_VISC_Y = 16;
 constexpr int K_VISC_Z = 17;
 constexpr int K_MOM_RHS = 18;
+constexpr int K_IB = 19;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -1210,6 +1212,60 @@ fsei_status fsei_momentum_rhs(fsei_plan* p, const double* u, const double* v, co
             hipLaunchKernelGGL((k_momentum_rhs<256, 16>), dim3(nb), dim3(256), 0, S(p), a);
         else
             hipLaunchKernelGGL((k_momentum_rhs<256, 1>), dim3(nb), dim3(256), 0, S(p), a);
+    }
+    return check_hip();
+}
+
+fsei_status ib_setup(fsei_plan* p, int comp, const double* xb, long nb, IbArgs* a) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (comp < 0 || comp > 2 || nb < 0 || (nb > 0 && !xb)) return FSEI_ERR_ARG;
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return FSEI_ERR_SIZE;
+    *a = IbArgs{};
+    a->nx = p->nx;
+    a->ny = p->ny;
+    a->nz = p->nz;
+    a->perx = p->bcx == FSEI_BC_PERIODIC;
+    a->pery = p->bcy == FSEI_BC_PERIODIC;
+    a->comp = comp;
+    a->nb = nb;
+    a->dx = p->dx;
+    a->dy = p->dy;
+    a->zn = tab<double>(p, comp == 2 ? T_ZF : T_ZM);
+    a->hz = tab<double>(p, comp == 2 ? T_HF : T_DZ);
+    a->xb = xb;
+    return FSEI_OK;
+}
+
+fsei_status fsei_ib_interpolate(fsei_plan* p, int comp, const double* field, const double* xb, long nb,
+                                double* ub) {
+    IbArgs a;
+    fsei_status st = ib_setup(p, comp, xb, nb, &a);
+    if (st != FSEI_OK) return st;
+    if (nb > 0 && (!field || !ub)) return FSEI_ERR_ARG;
+    if (nb == 0) return FSEI_OK;
+    a.field = const_cast<double*>(field);
+    a.ub = ub;
+    {
+        Timed t(p, K_IB);
+        hipLaunchKernelGGL(k_ib_interpolate, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
+    }
+    return check_hip();
+}
+
+fsei_status fsei_ib_spread(fsei_plan* p, int comp, double* field, const double* xb, const double* fb,
+                           const double* dvb, long nb) {
+    IbArgs a;
+    fsei_status st = ib_setup(p, comp, xb, nb, &a);
+    if (st != FSEI_OK) return st;
+    if (nb > 0 && (!field || !fb || !dvb)) return FSEI_ERR_ARG;
+    if (nb == 0) return FSEI_OK;
+    a.field = field;
+    a.fb = fb;
+    a.dvb = dvb;
+    {
+        Timed t(p, K_IB);
+        hipLaunchKernelGGL(k_ib_spread, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
     }
     return check_hip();
 }

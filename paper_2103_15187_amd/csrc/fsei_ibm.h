@@ -1,0 +1,173 @@
+// fsei_ibm.h -- immersed-boundary moving-least-squares (IB-MLS) transfer
+// between Lagrangian markers and one staggered velocity component.
+//
+// Paper, Sec. 2.1 (eq. interpv, Fig. mls): each marker x_b has a support of
+// 3 x 3 x 3 nodes of the component's own lattice; the velocity at the marker
+// is sum_k phi_k u_k with moving-least-squares operators on the linear basis
+// [1, x, y, z] and an exponential weight centred on the marker; the force
+// computed at the marker goes back to the same nodes as a distributed forcing.
+//
+//     A = sum_k W_k p_k p_k^T,  p_k = [1, x_k - x_b, y_k - y_b, z_k - z_b],
+//     phi_k = W_k (A^-1 e_0) . p_k,
+//     W_k = exp(-(dx_k/dx)^2 - (dy_k/dy)^2 - (dz_k/hz)^2),
+//
+// hz the z extent of the support's middle node (cell width for centre
+// values, centre distance for w faces).  Supports are the three nodes around
+// the nearest one, shifted inwards at walls and wrapped in periodic
+// directions (displacements to the nearest periodic image).  One lane per
+// marker; A is symmetric positive definite and is factored by Cholesky.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fsei_plan.h"
+
+namespace fsei {
+namespace dev {
+
+struct IbArgs {
+    int nx, ny, nz, perx, pery, comp;
+    long nb;
+    double dx, dy;
+    const double* zn;    // z of the component's nodes (faces for w, centres otherwise), nz
+    const double* hz;    // z extent of each node's control volume, nz
+    const double* xb;    // markers (nb, 3)
+    double* field;       // interpolate: read; spread: += (atomic)
+    double* ub;          // interpolate: out (nb)
+    const double* fb;    // spread: marker values (nb)
+    const double* dvb;   // spread: marker volumes (nb)
+};
+
+// support along a uniform axis: first index and displacements of its 3 nodes
+__device__ __forceinline__ void ib_axis(double xb, double x0, double d, int n, bool per, int (&idx)[3],
+                                        double (&dis)[3]) {
+    double t = (xb - x0) / d;
+    if (!(t == t)) t = 0.0;                       // NaN position: any in-grid support
+    t = fmin(fmax(t, -1.0e9), 1.0e9);
+    long m = (long)floor(t + 0.5);
+    const double L = d * n;
+    if (per) {
+        m = ((m % n) + n) % n;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int i = (int)((m + q - 1 + n) % n);
+            double dd = x0 + i * d - xb;
+            dd -= L * rint(dd / L);
+            idx[q] = i;
+            dis[q] = dd;
+        }
+    } else {
+        m = m < 1 ? 1 : (m > n - 2 ? n - 2 : m);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            idx[q] = (int)(m + q - 1);
+            dis[q] = x0 + idx[q] * d - xb;
+        }
+    }
+}
+
+// support along z: nearest node by bisection on the node coordinates
+__device__ __forceinline__ int ib_zmid(const double* __restrict__ zn, int n, double zb) {
+    int lo = 0, hi = n - 1;   // zn increasing
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (zn[mid] <= zb) lo = mid;
+        else hi = mid;
+    }
+    int m = (fabs(zn[hi] - zb) < fabs(zn[lo] - zb)) ? hi : lo;
+    return m < 1 ? 1 : (m > n - 2 ? n - 2 : m);
+}
+
+// operators phi (27) and flat indices (27) of one marker
+__device__ __forceinline__ void ib_shape(const IbArgs& a, long b, double (&phi)[27], size_t (&flat)[27]) {
+    const double xbx = a.xb[3 * b], xby = a.xb[3 * b + 1], xbz = a.xb[3 * b + 2];
+    int ix[3], iy[3], iz[3];
+    double dx[3], dy[3], dz[3];
+    ib_axis(xbx, a.comp == 0 ? 0.0 : 0.5 * a.dx, a.dx, a.nx, a.perx, ix, dx);
+    ib_axis(xby, a.comp == 1 ? 0.0 : 0.5 * a.dy, a.dy, a.ny, a.pery, iy, dy);
+    const int mz = ib_zmid(a.zn, a.nz, (xbz == xbz) ? xbz : 0.0);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        iz[q] = mz + q - 1;
+        dz[q] = a.zn[iz[q]] - xbz;
+    }
+    const double hz = a.hz[mz];
+    // weights and the moment matrix (upper triangle)
+    double W[27];
+    double m00 = 0, m01 = 0, m02 = 0, m03 = 0, m11 = 0, m12 = 0, m13 = 0, m22 = 0, m23 = 0, m33 = 0;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) {
+                const int q = (kk * 3 + jj) * 3 + ii;
+                const double px = dx[ii], py = dy[jj], pz = dz[kk];
+                const double rx = px / a.dx, ry = py / a.dy, rz = pz / hz;
+                const double w = exp(-(rx * rx) - (ry * ry) - (rz * rz));
+                W[q] = w;
+                m00 += w;
+                m01 += w * px;
+                m02 += w * py;
+                m03 += w * pz;
+                m11 += w * px * px;
+                m12 += w * px * py;
+                m13 += w * px * pz;
+                m22 += w * py * py;
+                m23 += w * py * pz;
+                m33 += w * pz * pz;
+                flat[q] = ((size_t)iz[kk] * a.ny + iy[jj]) * a.nx + ix[ii];
+            }
+    // c = A^-1 e_0 by Cholesky A = L L^T: solve L y = e_0, L^T c = y
+    const double l00 = sqrt(m00);
+    const double l10 = m01 / l00, l20 = m02 / l00, l30 = m03 / l00;
+    const double l11 = sqrt(m11 - l10 * l10);
+    const double l21 = (m12 - l20 * l10) / l11, l31 = (m13 - l30 * l10) / l11;
+    const double l22 = sqrt(m22 - l20 * l20 - l21 * l21);
+    const double l32 = (m23 - l30 * l20 - l31 * l21) / l22;
+    const double l33 = sqrt(m33 - l30 * l30 - l31 * l31 - l32 * l32);
+    const double y0 = 1.0 / l00;
+    const double y1 = -l10 * y0 / l11;
+    const double y2 = -(l20 * y0 + l21 * y1) / l22;
+    const double y3 = -(l30 * y0 + l31 * y1 + l32 * y2) / l33;
+    const double c3 = y3 / l33;
+    const double c2 = (y2 - l32 * c3) / l22;
+    const double c1 = (y1 - l21 * c2 - l31 * c3) / l11;
+    const double c0 = (y0 - l10 * c1 - l20 * c2 - l30 * c3) / l00;
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) {
+                const int q = (kk * 3 + jj) * 3 + ii;
+                phi[q] = W[q] * (c0 + c1 * dx[ii] + c2 * dy[jj] + c3 * dz[kk]);
+            }
+}
+
+__global__ __launch_bounds__(256) void k_ib_interpolate(IbArgs a) {
+    const long b = (long)blockIdx.x * 256 + threadIdx.x;
+    if (b >= a.nb) return;
+    double phi[27];
+    size_t flat[27];
+    ib_shape(a, b, phi, flat);
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) s += phi[q] * a.field[flat[q]];
+    a.ub[b] = s;
+}
+
+__global__ __launch_bounds__(256) void k_ib_spread(IbArgs a) {
+    const long b = (long)blockIdx.x * 256 + threadIdx.x;
+    if (b >= a.nb) return;
+    double phi[27];
+    size_t flat[27];
+    ib_shape(a, b, phi, flat);
+    const double s = a.fb[b] * a.dvb[b] / (a.dx * a.dy);
+    const size_t nxy = (size_t)a.nx * a.ny;
+#pragma unroll
+    for (int q = 0; q < 27; ++q) atomicAdd(a.field + flat[q], phi[q] * s / a.hz[flat[q] / nxy]);
+}
+
+}  // namespace dev
+}  // namespace fsei

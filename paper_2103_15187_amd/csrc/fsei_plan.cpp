@@ -107,7 +107,7 @@ void compute_layout(fsei_plan_impl* p) {
 static void build_tables(fsei_plan_impl* p) {
     const int nx = p->nx, ny = p->ny, nz = p->nz;
     size_t len[T_COUNT];
-    for (int t = T_ZA; t <= T_GAM_ADJ; ++t) len[t] = nz;
+    for (int t = T_ZA; t <= T_HF; ++t) len[t] = nz;
     len[T_LAMX] = nx;
     len[T_LAMY] = ny;
     len[T_TWX_C] = len[T_TWX_S] = len[T_DCTX_C] = len[T_DCTX_S] = nx;
@@ -140,6 +140,9 @@ static void build_tables(fsei_plan_impl* p) {
         T(T_H)[k] = h[k];
         T(T_ZETA_ADJ)[k] = (k <= nz - 2) ? 1.0L / h[k + 1] : 0.0L;
         T(T_GAM_ADJ)[k] = (k >= 1) ? 1.0L / dz[k - 1] : 0.0L;
+        T(T_ZF)[k] = p->zc[k];
+        T(T_ZM)[k] = zm[k];
+        T(T_HF)[k] = (k >= 1) ? h[k] : 0.5L * dz[0];
     }
     // modified wavenumbers of the 3-point second difference on each
     // transform row: DCT-II row q -> wavenumber q; half-complex row q ->

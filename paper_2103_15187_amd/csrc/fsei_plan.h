@@ -72,6 +72,9 @@ enum TableId {
     T_H,           // h_k = zm_k - zm_{k-1}, k>=1; 0 at k=0          (nz)
     T_ZETA_ADJ,    // 1/h_{k+1} for k<=nz-2, 0 at nz-1                (nz)
     T_GAM_ADJ,     // 1/dz_{k-1} for k>=1, 0 at k=0                   (nz)
+    T_ZF,          // z of face k (zc_k), k < nz                     (nz)
+    T_ZM,          // z of cell centre k, (zc_k + zc_{k+1})/2         (nz)
+    T_HF,          // z extent of the w-face volumes: h_k, k>=1; dz_0/2 (nz)
     T_LAMX,        // modified wavenumbers of x rows                  (nx)
     T_LAMY,        // modified wavenumbers of y rows                  (ny)
     T_TWX_C,       // cos(2 pi t / nx)                                (nx)

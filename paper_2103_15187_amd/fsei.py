@@ -73,6 +73,8 @@ def lib():
         "fsei_project_backward_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_viscous_solve": (I, [P, I, P, D]),
         "fsei_momentum_rhs": (I, [P, P, P, P, P, P, P, P, P, P, D, D, D, D]),
+        "fsei_ib_interpolate": (I, [P, I, P, P, ctypes.c_long, P]),
+        "fsei_ib_spread": (I, [P, I, P, P, P, P, ctypes.c_long]),
         "fsei_plan_set_timing": (I, [P, I]),
         "fsei_plan_reset_timing": (I, [P]),
         "fsei_plan_kernel_time": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_long),
@@ -249,6 +251,38 @@ class Plan:
                                        *(_ptr(a) for a in r), float(dt), float(re), float(gamma), float(rho)),
                "fsei_momentum_rhs")
         return r
+
+    def _markers(self, t, cols, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device.type != "cuda" \
+                or not t.is_contiguous() or (t.dim() != (2 if cols else 1)) or (cols and t.shape[1] != cols):
+            raise ValueError(f"{name} must be a contiguous float64 CUDA tensor of shape (nb{', 3' if cols else ''})")
+        return t
+
+    def ib_interpolate(self, field, comp, xb, ub=None):
+        """ub[b] = MLS interpolation of field (component comp) at marker xb[b]."""
+        import torch
+        field = self._field(field, torch.float64, "field")
+        xb = self._markers(xb, 3, "xb")
+        if ub is None:
+            ub = torch.empty(xb.shape[0], dtype=torch.float64, device=xb.device)
+        ub = self._markers(ub, 0, "ub")
+        self._stream()
+        _check(lib().fsei_ib_interpolate(self._h, int(comp), _ptr(field), _ptr(xb), xb.shape[0], _ptr(ub)),
+               "fsei_ib_interpolate")
+        return ub
+
+    def ib_spread(self, field, comp, xb, fb, dvb):
+        """field += MLS spreading of the marker values fb (volumes dvb)."""
+        import torch
+        field = self._field(field, torch.float64, "field")
+        xb = self._markers(xb, 3, "xb")
+        fb = self._markers(fb, 0, "fb")
+        dvb = self._markers(dvb, 0, "dvb")
+        self._stream()
+        _check(lib().fsei_ib_spread(self._h, int(comp), _ptr(field), _ptr(xb), _ptr(fb), _ptr(dvb), xb.shape[0]),
+               "fsei_ib_spread")
+        return field
 
     def viscous_step(self, u, v, w, beta):
         """viscous_solve of the three components, each in place."""
