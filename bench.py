@@ -45,7 +45,7 @@ SLOT_KERNEL = {
                     "grad_resid": "k_grad_resid<256, 16, false>"},
     "viscous_fp64": {"visc_x": "k_visc_x<16>", "visc_y": "k_visc_strided<2, 16>",
                      "visc_z": "k_visc_strided<2, 24>"},
-    "momentum_fp64": {"momentum_rhs": "k_momentum_rhs_pairs<256, 16>"},
+    "momentum_fp64": {"momentum_rhs": "k_momentum_rhs_pairs<64, 16, true>"},
 }
 
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:

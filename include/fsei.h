@@ -174,6 +174,12 @@ fsei_status fsei_project_backward_f32(fsei_plan* plan, float* gu, float* gv, flo
  * new tables; otherwise the call only enqueues three kernels. */
 fsei_status fsei_viscous_solve(fsei_plan* plan, int component, double* q, double beta);
 
+/* As fsei_viscous_solve, with the increment added to the velocity in the
+ * same pass: u <- u + dq (the provisional velocity u* = u^n + du of the
+ * fractional step).  rhs is used as scratch (its contents on return are the
+ * x and y stages' intermediate, not dq); u must not alias rhs. */
+fsei_status fsei_viscous_solve_add(fsei_plan* plan, int component, double* rhs, double* u, double beta);
+
 /* Explicit right-hand side of the momentum step (paper, Sec. 2.1, eq.
  * NSdiscr0: Adams-Bashforth for the convective term with weights gamma, rho
  * (3/2, -1/2; 1, 0 for a first step), Crank-Nicolson for the viscous term;

@@ -686,7 +686,7 @@ void launch_visc_s_M(fsei_plan* p, const ViscArgs& a, int L, unsigned groups) {
 
 void launch_visc_strided(fsei_plan* p, const ViscArgs& a, int L, unsigned groups) {
     // two adjacent columns per lane (16-byte accesses) when the rows allow
-    if (a.ncol % 2 == 0 && aligned16(a.data))
+    if (a.ncol % 2 == 0 && aligned16(a.data) && (a.add == nullptr || aligned16(a.add)))
         launch_visc_s_M<2>(p, a, L, groups);
     else
         launch_visc_s_M<1>(p, a, L, groups);
@@ -1107,7 +1107,19 @@ fsei_status fsei_project_backward_f32(fsei_plan* p, float* gu, float* gv, float*
     return check_hip();
 }
 
+static fsei_status viscous_solve(fsei_plan* p, int comp, double* q, double beta, double* add);
+
 fsei_status fsei_viscous_solve(fsei_plan* p, int comp, double* q, double beta) {
+    return viscous_solve(p, comp, q, beta, nullptr);
+}
+
+fsei_status fsei_viscous_solve_add(fsei_plan* p, int comp, double* rhs, double* u, double beta) {
+    if (p && !u) return FSEI_ERR_ARG;
+    if (u && u == rhs) return FSEI_ERR_ARG;
+    return viscous_solve(p, comp, rhs, beta, u);
+}
+
+static fsei_status viscous_solve(fsei_plan* p, int comp, double* q, double beta, double* add) {
     fsei_status st = ready(p);
     if (st != FSEI_OK) return st;
     if (!q || comp < 0 || comp > 2 || !std::isfinite(beta) || !(beta > 0.0)) return FSEI_ERR_ARG;
@@ -1154,6 +1166,7 @@ fsei_status fsei_viscous_solve(fsei_plan* p, int comp, double* q, double beta) {
     a.cyc = 0;
     a.rstride = (size_t)p->nx * p->ny;
     a.bstride = (size_t)p->nx;
+    a.add = add;   // the last pass adds its result to `add` when given
     {
         Timed t(p, K_VISC_Z);
         launch_visc_strided(p, a, p->visc_L[2], (unsigned)p->ny);
@@ -1204,10 +1217,12 @@ fsei_status fsei_momentum_rhs(fsei_plan* p, const double* u, const double* v, co
         const bool pairs = p->nx % 2 == 0 && aligned16(u) && aligned16(v) && aligned16(w) && aligned16(nu) &&
                            aligned16(nv) && aligned16(nw) && aligned16(ru) && aligned16(rv) && aligned16(rw);
         const bool t16 = p->ny % 16 == 0;
+        // one wave per row (measured fastest at 512x512x768: 64 lanes 4.49 ms, 128 4.61, 256 5.15),
+        // outputs stored non-temporally (nothing re-reads them in this pass)
         if (pairs && t16)
-            hipLaunchKernelGGL((k_momentum_rhs_pairs<256, 16>), dim3(nb), dim3(256), 0, S(p), a);
+            hipLaunchKernelGGL((k_momentum_rhs_pairs<64, 16, true>), dim3(nb), dim3(64), 0, S(p), a);
         else if (pairs)
-            hipLaunchKernelGGL((k_momentum_rhs_pairs<256, 1>), dim3(nb), dim3(256), 0, S(p), a);
+            hipLaunchKernelGGL((k_momentum_rhs_pairs<64, 1, true>), dim3(nb), dim3(64), 0, S(p), a);
         else if (t16)
             hipLaunchKernelGGL((k_momentum_rhs<256, 16>), dim3(nb), dim3(256), 0, S(p), a);
         else

@@ -196,7 +196,7 @@ __global__ __launch_bounds__(NT) void k_momentum_rhs(MomArgs a) {
 // i0 + 1), i0 even: every row the stencils touch is read as one aligned
 // 16-byte pair plus its two x neighbours, each (row, column) once per lane.
 // Needs nx even and 16-byte aligned fields.  Same tile order as above.
-template <int NT, int GJ>
+template <int NT, int GJ, bool NTS = false>   // NTS: non-temporal stores of the six outputs
 __global__ __launch_bounds__(NT) void k_momentum_rhs_pairs(MomArgs a) {
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -359,12 +359,22 @@ __global__ __launch_bounds__(NT) void k_momentum_rhs_pairs(MomArgs a) {
                 nw[c] = n;
             }
         }
-        *reinterpret_cast<double2*>(a.ru + row + i0) = make_double2(ru[0], ru[1]);
-        *reinterpret_cast<double2*>(a.rv + row + i0) = make_double2(rv[0], rv[1]);
-        *reinterpret_cast<double2*>(a.rw + row + i0) = make_double2(rw[0], rw[1]);
-        *reinterpret_cast<double2*>(a.nu + row + i0) = make_double2(nu[0], nu[1]);
-        *reinterpret_cast<double2*>(a.nv + row + i0) = make_double2(nv[0], nv[1]);
-        *reinterpret_cast<double2*>(a.nw + row + i0) = make_double2(nw[0], nw[1]);
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        auto put = [&](double* q, double x0, double x1) {
+            d2 v;
+            v.x = x0;
+            v.y = x1;
+            if constexpr (NTS)
+                __builtin_nontemporal_store(v, reinterpret_cast<d2*>(q + row + i0));
+            else
+                *reinterpret_cast<d2*>(q + row + i0) = v;
+        };
+        put(a.ru, ru[0], ru[1]);
+        put(a.rv, rv[0], rv[1]);
+        put(a.rw, rw[0], rw[1]);
+        put(a.nu, nu[0], nu[1]);
+        put(a.nv, nv[0], nv[1]);
+        put(a.nw, nw[0], nw[1]);
     }
 }
 

@@ -44,6 +44,8 @@ struct ViscArgs {
     int n;              // rows of a line
     int cyc;            // periodic line (Sherman-Morrison correction)
     int vec;            // x kernel: n even and data 16-byte aligned (16-byte staging accesses)
+    double* add;        // strided kernel: if set, the result is added here (same layout) instead of
+                        // stored over data
     int ncol;           // strided kernel: columns (lines side by side along x)
     long nlines;        // x kernel: number of lines
     size_t rstride;     // strided kernel: elements between consecutive rows of a line
@@ -248,7 +250,8 @@ __global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided(ViscArgs a) {
     // store addresses rebuilt here (not kept live from the loads)
     size_t off = (size_t)blockIdx.y * a.bstride + q0 + (size_t)s0 * a.rstride;
     asm volatile("" : "+v"(off));
-    base = a.data + off - (size_t)s0 * a.rstride;
+    const bool acc = a.add != nullptr;   // uniform
+    base = (acc ? a.add : a.data) + off - (size_t)s0 * a.rstride;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
         const int k = s0 + t;
@@ -261,11 +264,16 @@ __global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided(ViscArgs a) {
 #pragma unroll
                     for (int h = 0; h < M; ++h) v[h] = F[h][t];
                 }
-                *reinterpret_cast<V*>(base + (size_t)k * a.rstride) = v;
+                V* q = reinterpret_cast<V*>(base + (size_t)k * a.rstride);
+                if (acc) v += *q;
+                *q = v;
             } else {
 #pragma unroll
                 for (int h = 0; h < M; ++h)
-                    if (q0 + h < a.ncol) base[(size_t)k * a.rstride + h] = F[h][t];
+                    if (q0 + h < a.ncol) {
+                        double* q = base + (size_t)k * a.rstride + h;
+                        *q = acc ? *q + F[h][t] : F[h][t];
+                    }
             }
         }
     }

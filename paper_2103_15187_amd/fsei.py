@@ -72,6 +72,7 @@ def lib():
         "fsei_project_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_project_backward_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_viscous_solve": (I, [P, I, P, D]),
+        "fsei_viscous_solve_add": (I, [P, I, P, P, D]),
         "fsei_momentum_rhs": (I, [P, P, P, P, P, P, P, P, P, P, D, D, D, D]),
         "fsei_ib_interpolate": (I, [P, I, P, P, ctypes.c_long, P]),
         "fsei_ib_spread": (I, [P, I, P, P, P, P, ctypes.c_long]),
@@ -283,6 +284,17 @@ class Plan:
         _check(lib().fsei_ib_spread(self._h, int(comp), _ptr(field), _ptr(xb), _ptr(fb), _ptr(dvb), xb.shape[0]),
                "fsei_ib_spread")
         return field
+
+    def viscous_solve_add(self, rhs, u, component, beta):
+        """In place: u <- u + dq with (I - beta Lx)(I - beta Ly)(I - beta Lz) dq = rhs
+        (rhs is used as scratch)."""
+        import torch
+        rhs = self._field(rhs, torch.float64, "rhs")
+        u = self._field(u, torch.float64, "u")
+        self._stream()
+        _check(lib().fsei_viscous_solve_add(self._h, int(component), _ptr(rhs), _ptr(u), float(beta)),
+               "fsei_viscous_solve_add")
+        return u
 
     def viscous_step(self, u, v, w, beta):
         """viscous_solve of the three components, each in place."""

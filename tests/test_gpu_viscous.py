@@ -68,6 +68,24 @@ def test_viscous_solve_matches_oracle(dims, bc):
             assert np.all(got[V.dead_mask(g, comp)] == 0.0)
 
 
+@pytest.mark.parametrize("bc", [(WALL, WALL), (PERIODIC, WALL)])
+def test_viscous_solve_add_matches_oracle(bc):
+    """u <- u + dq in the same pass (odd nx: one column per lane, even: two)."""
+    for dims in ((24, 18, 20), (27, 9, 33)):
+        spec = W.GridSpec(*dims, bc[0], bc[1], 1.3, 0.9, 1.7, 2.0)
+        g = grid_of(spec)
+        F = fsei()
+        plan = F.Plan.from_spec(spec)
+        r = W.rng(71).standard_normal((2,) + spec.shape)
+        beta = 0.7 * spec.dx**2
+        for comp in range(3):
+            rhs, u = dev(r[0]), dev(r[1])
+            plan.viscous_solve_add(rhs, u, comp, beta)
+            torch.cuda.synchronize()
+            ref = r[1] + V.viscous_solve(r[0], g, comp, beta)
+            assert np.abs(host(u) - ref).max() <= 1e-12 * np.abs(ref).max(), (dims, comp)
+
+
 def test_viscous_tables_follow_beta_and_component():
     """Alternating beta and component rebuild and reuse the tables correctly."""
     spec = W.GridSpec(32, 24, 36, PERIODIC, WALL, 1.0, 1.0, 1.0, 2.2)
