@@ -176,19 +176,19 @@ def gpu_momentum(spec, u0, v0, w0, steps, warmup, torch, fsei):
     return res
 
 
-def gpu_ib(spec, u0, steps, warmup, torch, fsei, nb=1_000_000):
-    """Time `steps` IB-MLS transfers of nb markers (interpolation of the three
-    velocity components at the markers, then spreading of one value per
-    marker and component back to the grid).  Markers: uniform in the domain."""
-    import numpy as np
+def gpu_ib(spec, u0, steps, warmup, torch, fsei):
+    """Time `steps` IB-MLS transfers (interpolation of the three velocity
+    components at the markers, then spreading of one value per marker and
+    component back to the grid).  Markers: the ~10^6 triangle centroids of a
+    prolate spheroid surface centred in the domain, about one triangle per
+    grid cell face, in mesh order."""
     from paper_2103_15187_amd import workloads as W
     plan = fsei.Plan.from_spec(spec)
-    r = W.rng(123)
-    zc = spec.zc()
-    xb = np.stack([r.uniform(0, spec.lx, nb), r.uniform(0, spec.ly, nb), r.uniform(zc[0], zc[-1], nb)], 1)
+    xb, dv = W.spheroid_markers(spec)
+    nb = len(xb)
     xd = torch.from_numpy(xb).to(u0.device)
     fb = torch.ones(nb, dtype=torch.float64, device=u0.device)
-    dvb = torch.full((nb,), spec.dx * spec.dy * 1e-3, dtype=torch.float64, device=u0.device)
+    dvb = torch.from_numpy(dv).to(u0.device)
     ub = torch.empty(nb, dtype=torch.float64, device=u0.device)
     f = torch.zeros_like(u0)
 
@@ -216,7 +216,8 @@ def gpu_ib(spec, u0, steps, warmup, torch, fsei, nb=1_000_000):
     return {"ms_per_step": round(ms, 4), "markers": nb, "markers_per_s": round(nb / (ms / 1e3), 1),
             "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()},
             "note": "one step = interpolation of u, v, w at every marker + spreading of one value per marker "
-                    "and component (27-node MLS supports, FP64 atomics); markers uniform in the 512x512x768 domain"}
+                    "and component (27-node MLS supports, FP64 atomics); markers: triangle centroids of a prolate "
+                    "spheroid (semi-axes 1.2, 1.2, 2.4) centred in the 512x512x768 domain, mesh order"}
 
 
 def divergence_max(u, v, w, spec, torch):

@@ -10,7 +10,8 @@ LIB = os.path.join(PKG, "libfsei.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["fsei_api.hip", "fsei_plan.cpp"]
-HEADERS = ["fsei_plan.h", "fsei_fft.h", "fsei_transforms.h", "fsei_kernels.h"]
+HEADERS = ["fsei_plan.h", "fsei_fft.h", "fsei_transforms.h", "fsei_kernels.h", "fsei_viscous.h",
+           "fsei_momentum.h", "fsei_ibm.h"]
 
 # -packed-fp32-ops: hipcc -O3 may otherwise emit packed FP32 instructions
 # from ordinary float code; this keeps them out of every kernel.

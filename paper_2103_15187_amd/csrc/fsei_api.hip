@@ -1263,7 +1263,10 @@ fsei_status fsei_ib_interpolate(fsei_plan* p, int comp, const double* field, con
     a.ub = ub;
     {
         Timed t(p, K_IB);
-        hipLaunchKernelGGL(k_ib_interpolate, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
+        if (p->ncells() < ((size_t)1 << 32))
+            hipLaunchKernelGGL(k_ib_interpolate<uint32_t>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
+        else
+            hipLaunchKernelGGL(k_ib_interpolate<size_t>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
     }
     return check_hip();
 }
@@ -1280,7 +1283,10 @@ fsei_status fsei_ib_spread(fsei_plan* p, int comp, double* field, const double* 
     a.dvb = dvb;
     {
         Timed t(p, K_IB);
-        hipLaunchKernelGGL(k_ib_spread, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
+        if (p->ncells() < ((size_t)1 << 32))
+            hipLaunchKernelGGL(k_ib_spread<uint32_t>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
+        else
+            hipLaunchKernelGGL(k_ib_spread<size_t>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
     }
     return check_hip();
 }

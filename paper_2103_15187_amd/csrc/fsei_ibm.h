@@ -78,95 +78,143 @@ __device__ __forceinline__ int ib_zmid(const double* __restrict__ zn, int n, dou
     return m < 1 ? 1 : (m > n - 2 ? n - 2 : m);
 }
 
-// operators phi (27) and flat indices (27) of one marker
-__device__ __forceinline__ void ib_shape(const IbArgs& a, long b, double (&phi)[27], size_t (&flat)[27]) {
-    const double xbx = a.xb[3 * b], xby = a.xb[3 * b + 1], xbz = a.xb[3 * b + 2];
+// support of one marker: node indices and marker-node displacements per
+// axis, and the z scale of the weight (extent of the middle node's volume)
+struct IbSupport {
     int ix[3], iy[3], iz[3];
     double dx[3], dy[3], dz[3];
-    ib_axis(xbx, a.comp == 0 ? 0.0 : 0.5 * a.dx, a.dx, a.nx, a.perx, ix, dx);
-    ib_axis(xby, a.comp == 1 ? 0.0 : 0.5 * a.dy, a.dy, a.ny, a.pery, iy, dy);
+    double hz;
+};
+
+__device__ __forceinline__ IbSupport ib_support(const IbArgs& a, long b) {
+    IbSupport s;
+    const double xbx = a.xb[3 * b], xby = a.xb[3 * b + 1], xbz = a.xb[3 * b + 2];
+    ib_axis(xbx, a.comp == 0 ? 0.0 : 0.5 * a.dx, a.dx, a.nx, a.perx, s.ix, s.dx);
+    ib_axis(xby, a.comp == 1 ? 0.0 : 0.5 * a.dy, a.dy, a.ny, a.pery, s.iy, s.dy);
     const int mz = ib_zmid(a.zn, a.nz, (xbz == xbz) ? xbz : 0.0);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        iz[q] = mz + q - 1;
-        dz[q] = a.zn[iz[q]] - xbz;
+        s.iz[q] = mz + q - 1;
+        s.dz[q] = a.zn[s.iz[q]] - xbz;
     }
-    const double hz = a.hz[mz];
-    // weights and the moment matrix (upper triangle)
-    double W[27];
+    s.hz = a.hz[mz];
+    return s;
+}
+
+__device__ __forceinline__ double ib_weight(const IbArgs& a, const IbSupport& s, int ii, int jj, int kk) {
+    const double rx = s.dx[ii] / a.dx, ry = s.dy[jj] / a.dy, rz = s.dz[kk] / s.hz;
+    return exp(-(rx * rx) - (ry * ry) - (rz * rz));
+}
+
+// flat offset of node (ii, jj, kk) of the support; IT: 32-bit offsets when
+// the field has fewer than 2^32 cells, else 64-bit
+template <typename IT>
+__device__ __forceinline__ IT ib_flat(const IbArgs& a, const IbSupport& s, int ii, int jj, int kk) {
+    return ((IT)s.iz[kk] * (IT)a.ny + (IT)s.iy[jj]) * (IT)a.nx + (IT)s.ix[ii];
+}
+
+// moment matrix A (upper triangle) of the support
+struct IbMoments {
     double m00 = 0, m01 = 0, m02 = 0, m03 = 0, m11 = 0, m12 = 0, m13 = 0, m22 = 0, m23 = 0, m33 = 0;
-#pragma unroll
-    for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-            for (int ii = 0; ii < 3; ++ii) {
-                const int q = (kk * 3 + jj) * 3 + ii;
-                const double px = dx[ii], py = dy[jj], pz = dz[kk];
-                const double rx = px / a.dx, ry = py / a.dy, rz = pz / hz;
-                const double w = exp(-(rx * rx) - (ry * ry) - (rz * rz));
-                W[q] = w;
-                m00 += w;
-                m01 += w * px;
-                m02 += w * py;
-                m03 += w * pz;
-                m11 += w * px * px;
-                m12 += w * px * py;
-                m13 += w * px * pz;
-                m22 += w * py * py;
-                m23 += w * py * pz;
-                m33 += w * pz * pz;
-                flat[q] = ((size_t)iz[kk] * a.ny + iy[jj]) * a.nx + ix[ii];
-            }
-    // c = A^-1 e_0 by Cholesky A = L L^T: solve L y = e_0, L^T c = y
-    const double l00 = sqrt(m00);
-    const double l10 = m01 / l00, l20 = m02 / l00, l30 = m03 / l00;
-    const double l11 = sqrt(m11 - l10 * l10);
-    const double l21 = (m12 - l20 * l10) / l11, l31 = (m13 - l30 * l10) / l11;
-    const double l22 = sqrt(m22 - l20 * l20 - l21 * l21);
-    const double l32 = (m23 - l30 * l20 - l31 * l21) / l22;
-    const double l33 = sqrt(m33 - l30 * l30 - l31 * l31 - l32 * l32);
+    __device__ __forceinline__ void add(double w, double px, double py, double pz) {
+        m00 += w;
+        m01 += w * px;
+        m02 += w * py;
+        m03 += w * pz;
+        m11 += w * px * px;
+        m12 += w * px * py;
+        m13 += w * px * pz;
+        m22 += w * py * py;
+        m23 += w * py * pz;
+        m33 += w * pz * pz;
+    }
+};
+
+// c = A^-1 e_0 by Cholesky A = L L^T (solve L y = e_0, then L^T c = y); the
+// operator of node k is then phi_k = W_k (c0 + c1 dx_k + c2 dy_k + c3 dz_k)
+__device__ __forceinline__ void ib_coeffs(const IbMoments& m, double (&c)[4]) {
+    const double l00 = sqrt(m.m00);
+    const double l10 = m.m01 / l00, l20 = m.m02 / l00, l30 = m.m03 / l00;
+    const double l11 = sqrt(m.m11 - l10 * l10);
+    const double l21 = (m.m12 - l20 * l10) / l11, l31 = (m.m13 - l30 * l10) / l11;
+    const double l22 = sqrt(m.m22 - l20 * l20 - l21 * l21);
+    const double l32 = (m.m23 - l30 * l20 - l31 * l21) / l22;
+    const double l33 = sqrt(m.m33 - l30 * l30 - l31 * l31 - l32 * l32);
     const double y0 = 1.0 / l00;
     const double y1 = -l10 * y0 / l11;
     const double y2 = -(l20 * y0 + l21 * y1) / l22;
     const double y3 = -(l30 * y0 + l31 * y1 + l32 * y2) / l33;
-    const double c3 = y3 / l33;
-    const double c2 = (y2 - l32 * c3) / l22;
-    const double c1 = (y1 - l21 * c2 - l31 * c3) / l11;
-    const double c0 = (y0 - l10 * c1 - l20 * c2 - l30 * c3) / l00;
+    c[3] = y3 / l33;
+    c[2] = (y2 - l32 * c[3]) / l22;
+    c[1] = (y1 - l21 * c[2] - l31 * c[3]) / l11;
+    c[0] = (y0 - l10 * c[1] - l20 * c[2] - l30 * c[3]) / l00;
+}
+
+// u(x_b) = sum_k phi_k u_k = c0 S0 + c1 S1 + c2 S2 + c3 S3 with
+// S = sum_k W_k [1, dx_k, dy_k, dz_k] u_k: the 27 gathers are issued first and
+// the weights, moments and value sums formed in one pass while they land
+template <typename IT>
+__global__ __launch_bounds__(256) void k_ib_interpolate(IbArgs a) {
+    const long b = (long)blockIdx.x * 256 + threadIdx.x;
+    if (b >= a.nb) return;
+    const IbSupport s = ib_support(a, b);
+    double val[27];
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) val[(kk * 3 + jj) * 3 + ii] = a.field[ib_flat<IT>(a, s, ii, jj, kk)];
+    IbMoments m;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
     for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj)
 #pragma unroll
             for (int ii = 0; ii < 3; ++ii) {
-                const int q = (kk * 3 + jj) * 3 + ii;
-                phi[q] = W[q] * (c0 + c1 * dx[ii] + c2 * dy[jj] + c3 * dz[kk]);
+                const double w = ib_weight(a, s, ii, jj, kk);
+                m.add(w, s.dx[ii], s.dy[jj], s.dz[kk]);
+                const double wv = w * val[(kk * 3 + jj) * 3 + ii];
+                s0 += wv;
+                s1 += wv * s.dx[ii];
+                s2 += wv * s.dy[jj];
+                s3 += wv * s.dz[kk];
             }
+    double c[4];
+    ib_coeffs(m, c);
+    a.ub[b] = c[0] * s0 + c[1] * s1 + c[2] * s2 + c[3] * s3;
 }
 
-__global__ __launch_bounds__(256) void k_ib_interpolate(IbArgs a) {
-    const long b = (long)blockIdx.x * 256 + threadIdx.x;
-    if (b >= a.nb) return;
-    double phi[27];
-    size_t flat[27];
-    ib_shape(a, b, phi, flat);
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < 27; ++q) s += phi[q] * a.field[flat[q]];
-    a.ub[b] = s;
-}
-
+// f_k += phi_k F_b dV_b / (dx dy hz_k): moments first, then the weights are
+// recomputed (the same arithmetic, so the same values) for the atomic adds,
+// so no per-node array stays live
+template <typename IT>
 __global__ __launch_bounds__(256) void k_ib_spread(IbArgs a) {
     const long b = (long)blockIdx.x * 256 + threadIdx.x;
     if (b >= a.nb) return;
-    double phi[27];
-    size_t flat[27];
-    ib_shape(a, b, phi, flat);
-    const double s = a.fb[b] * a.dvb[b] / (a.dx * a.dy);
-    const size_t nxy = (size_t)a.nx * a.ny;
+    const IbSupport s = ib_support(a, b);
+    IbMoments m;
 #pragma unroll
-    for (int q = 0; q < 27; ++q) atomicAdd(a.field + flat[q], phi[q] * s / a.hz[flat[q] / nxy]);
+    for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) m.add(ib_weight(a, s, ii, jj, kk), s.dx[ii], s.dy[jj], s.dz[kk]);
+    double c[4];
+    ib_coeffs(m, c);
+    const double f = a.fb[b] * a.dvb[b] / (a.dx * a.dy);
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+        const double hk = a.hz[s.iz[kk]];   // control-volume z extent of the plane's nodes
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+            for (int ii = 0; ii < 3; ++ii) {
+                const double phi = ib_weight(a, s, ii, jj, kk) * (c[0] + c[1] * s.dx[ii] + c[2] * s.dy[jj] + c[3] * s.dz[kk]);
+                atomicAdd(a.field + ib_flat<IT>(a, s, ii, jj, kk), phi * f / hk);
+            }
+    }
 }
 
 }  // namespace dev

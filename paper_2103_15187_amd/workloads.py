@@ -201,3 +201,40 @@ def face_weights_random(spec: GridSpec, seed: int):
 def small_spec(nx, ny, nz, bcx=WALL, bcy=WALL, lx=None, ly=None, lz=1.0, stretch=1.5):
     """Helper for tiny test grids."""
     return GridSpec(nx, ny, nz, bcx, bcy, lx if lx else 1.0, ly if ly else 1.0, lz, stretch)
+
+
+def uniform_markers(spec: GridSpec, nb: int, seed: int) -> np.ndarray:
+    """nb Lagrangian marker positions (nb, 3), uniform in the domain."""
+    g = rng(seed)
+    zc = spec.zc()
+    return np.stack([g.uniform(0, spec.lx, nb), g.uniform(0, spec.ly, nb), g.uniform(zc[0], zc[-1], nb)], 1)
+
+
+def spheroid_markers(spec: GridSpec, radius: float = 1.2, height: float = 2.4):
+    """Markers of a wet surface: the centroids of a triangulated prolate
+    spheroid (semi-axes radius, radius, height) centred in the domain, with
+    about one triangle per dx * dy of surface, since the paper refines its
+    surface meshes until every tile is smaller than the local grid spacing
+    (Sec. 4).  A latitude-longitude mesh: each quad is split in two triangles;
+    markers come out in mesh order (neighbours in memory are neighbours on the
+    surface; the collapsed triangles at the poles are dropped), and each marker's volume is its triangle's area times dx.
+
+    Returns (xb (nb, 3), dv (nb,))."""
+    c0 = np.array([0.5 * spec.lx, 0.5 * spec.ly, 0.5 * spec.zc()[-1]])
+    h = np.sqrt(spec.dx * spec.dy)
+    # meridian length (Ramanujan's perimeter of the ellipse, halved) and equator
+    a, b = radius, height
+    meridian = 0.5 * np.pi * (3 * (a + b) - np.sqrt((3 * a + b) * (a + 3 * b)))
+    nt = max(2, int(np.ceil(meridian / (1.2 * h))))
+    npz = max(3, int(np.ceil(2 * np.pi * a / (1.2 * h))))
+    th = np.linspace(0.0, np.pi, nt + 1)
+    ph = np.linspace(0.0, 2 * np.pi, npz + 1)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    V = np.stack([a * np.sin(T) * np.cos(P), a * np.sin(T) * np.sin(P), b * np.cos(T)], -1) + c0
+    p00, p01, p10, p11 = V[:-1, :-1], V[:-1, 1:], V[1:, :-1], V[1:, 1:]
+    tri = np.stack([np.stack([p00, p10, p11], -2), np.stack([p00, p11, p01], -2)], 2)   # (nt, np, 2, 3, 3)
+    tri = tri.reshape(-1, 3, 3)
+    area = 0.5 * np.linalg.norm(np.cross(tri[:, 1] - tri[:, 0], tri[:, 2] - tri[:, 0]), axis=1)
+    keep = area > 1e-12 * h * h          # the collapsed triangles at the two poles
+    xb = tri[keep].mean(axis=1)
+    return np.ascontiguousarray(xb), area[keep] * spec.dx

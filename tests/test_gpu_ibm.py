@@ -117,3 +117,43 @@ def test_c3_ib_linear_reproduction_and_transpose():
         rhs = float((f * u * vol).sum())
         scale = float((dvb * fb.abs()).sum()) * float(u.abs().max())
         assert abs(lhs - rhs) <= 1e-12 * scale, (comp, lhs, rhs)
+
+
+@pytest.mark.timeout(400)
+def test_c3_ib_surface_markers_transpose_and_sampled_parity():
+    """~10^6 triangle centroids of a spheroid surface (clustered markers: many
+    atomic additions land on the same nodes).  Spreading must stay the
+    volume-weighted transpose of interpolation; sampled markers are compared
+    with the oracle one by one (the oracle's support only reads 27 nodes)."""
+    spec = W.CONFIGS["C3"]
+    F = fsei()
+    plan = F.Plan.from_spec(spec)
+    xb, dv = W.spheroid_markers(spec)
+    nb = len(xb)
+    xd, dvd = dev(xb), dev(dv)
+    zc = spec.zc()
+    zm = 0.5 * (zc[1:] + zc[:-1])
+    g = oracle.Grid(spec.nx, spec.ny, spec.nz, spec.bcx, spec.bcy, spec.dx, spec.dy, zc)
+    pick = W.rng(5).choice(nb, 200, replace=False)
+    for comp in range(3):
+        print(f"C3 surface ib comp={comp} nb={nb}", flush=True)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(10 + comp)
+        u = torch.randn(spec.shape, dtype=torch.float64, device="cuda", generator=gen)
+        fb = torch.randn(nb, dtype=torch.float64, device="cuda", generator=gen)
+        iu = plan.ib_interpolate(u, comp, xd)
+        f = torch.zeros_like(u)
+        plan.ib_spread(f, comp, xd, fb, dvd)
+        vz = (np.diff(zc) if comp != 2 else np.concatenate([[0.5 * (zc[1] - zc[0])], np.diff(zm)]))
+        vol = torch.tensor(spec.dx * spec.dy * vz, device="cuda").view(-1, 1, 1)
+        lhs = float((dvd * fb * iu).sum())
+        rhs = float((f * u * vol).sum())
+        scale = float((dvd * fb.abs()).sum()) * float(u.abs().max())
+        assert abs(lhs - rhs) <= 1e-12 * scale, (comp, lhs, rhs)
+        # sampled markers against the oracle's operators
+        uh = host(u).reshape(-1)
+        iuh = host(iu)
+        for b in pick:
+            flat, phi = IB.shape_functions(g, comp, xb[b])
+            ref = phi @ uh[flat]
+            assert abs(iuh[b] - ref) <= 1e-12 * np.abs(uh[flat]).max(), (comp, b)
