@@ -1283,8 +1283,8 @@ fsei_status fsei_ib_spread(fsei_plan* p, int comp, double* field, const double* 
     a.dvb = dvb;
     {
         Timed t(p, K_IB);
-        if (p->ncells() < ((size_t)1 << 32))
-            hipLaunchKernelGGL(k_ib_spread<uint32_t>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
+        if (p->ncells() <= (size_t)0xFFFFFFFEu)   // node offsets fit the LDS table's 32-bit keys
+            hipLaunchKernelGGL(k_ib_spread_lds, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
         else
             hipLaunchKernelGGL(k_ib_spread<size_t>, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, S(p), a);
     }

@@ -217,5 +217,71 @@ __global__ __launch_bounds__(256) void k_ib_spread(IbArgs a) {
     }
 }
 
+// Spreading with the adds of one workgroup's markers combined in LDS first.
+// Markers that come in mesh order (neighbours on the surface next to each
+// other) share most of their support nodes, so a workgroup's 256 x 27
+// contributions land on far fewer distinct nodes.  An open-addressing table
+// of kIbSlots (node offset, sum) pairs collects them (bounded linear probing;
+// a contribution that finds no slot goes straight to the global atomic), and
+// the filled slots are then added to the field, one global atomic each.
+// Needs 32-bit offsets: the empty key 0xFFFFFFFF is not a node offset.
+constexpr int kIbSlots = 4096;
+constexpr int kIbProbes = 8;
+constexpr unsigned kIbEmpty = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(256) void k_ib_spread_lds(IbArgs a) {
+    __shared__ unsigned skey[kIbSlots];
+    __shared__ double sval[kIbSlots];
+    for (int t = threadIdx.x; t < kIbSlots; t += 256) {
+        skey[t] = kIbEmpty;
+        sval[t] = 0.0;
+    }
+    __syncthreads();
+    const long b = (long)blockIdx.x * 256 + threadIdx.x;
+    if (b < a.nb) {
+        const IbSupport s = ib_support(a, b);
+        IbMoments m;
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < 3; ++ii) m.add(ib_weight(a, s, ii, jj, kk), s.dx[ii], s.dy[jj], s.dz[kk]);
+        double c[4];
+        ib_coeffs(m, c);
+        const double f = a.fb[b] * a.dvb[b] / (a.dx * a.dy);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+            const double hk = a.hz[s.iz[kk]];
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                for (int ii = 0; ii < 3; ++ii) {
+                    const double phi =
+                        ib_weight(a, s, ii, jj, kk) * (c[0] + c[1] * s.dx[ii] + c[2] * s.dy[jj] + c[3] * s.dz[kk]);
+                    const double v = phi * f / hk;
+                    const unsigned key = ib_flat<unsigned>(a, s, ii, jj, kk);
+                    unsigned h = (key * 2654435761u) >> 20;   // 12 bits: kIbSlots
+                    bool done = false;
+                    for (int pr = 0; pr < kIbProbes; ++pr) {
+                        const unsigned old = atomicCAS(&skey[h], kIbEmpty, key);
+                        if (old == kIbEmpty || old == key) {
+                            atomicAdd(&sval[h], v);
+                            done = true;
+                            break;
+                        }
+                        h = (h + 1) & (kIbSlots - 1);
+                    }
+                    if (!done) atomicAdd(a.field + key, v);
+                }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kIbSlots; t += 256) {
+        const unsigned key = skey[t];
+        if (key != kIbEmpty) atomicAdd(a.field + key, sval[t]);
+    }
+}
+
 }  // namespace dev
 }  // namespace fsei
