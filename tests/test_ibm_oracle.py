@@ -26,6 +26,17 @@ def markers(g, nb, seed):
     return np.stack([r.uniform(0, g.nx * g.dx, nb), r.uniform(0, g.ny * g.dy, nb), r.uniform(0, g.zc[-1], nb)], 1)
 
 
+def _volumes_z(g, comp):
+    """z extent of each node's control volume, written out here: the cell
+    width for u, v (cell centres in z); for w on face k the distance between
+    the centres around it, half the first cell at the wall face k = 0."""
+    zc = g.zc
+    if comp != 2:
+        return np.diff(zc)
+    zm = 0.5 * (zc[1:] + zc[:-1])
+    return np.concatenate([[0.5 * (zc[1] - zc[0])], np.diff(zm)])
+
+
 def _displacements(g, comp, xb, flat):
     x, y, z = I.node_coords(g, comp)
     kz, rem = np.divmod(flat, g.nx * g.ny)
@@ -61,7 +72,7 @@ def test_matches_weighted_least_squares_fit(comp):
     for b, x in enumerate(xb):
         flat, _ = I.shape_functions(g, comp, x)
         d = _displacements(g, comp, x, flat)
-        hz = I.node_volumes_z(g, comp)[np.divmod(flat, g.nx * g.ny)[0][13]]
+        hz = _volumes_z(g, comp)[np.divmod(flat, g.nx * g.ny)[0][13]]
         Wk = np.exp(-(d[:, 0] / g.dx) ** 2 - (d[:, 1] / g.dy) ** 2 - (d[:, 2] / hz) ** 2)
         P = np.concatenate([np.ones((27, 1)), d], 1)
         s = np.sqrt(Wk)
@@ -80,7 +91,26 @@ def test_spreading_is_the_volume_weighted_transpose(bc, comp):
     dv = r.uniform(0.5, 1.5, 50) * 1e-3
     u = r.standard_normal(g.shape)
     f = I.spread(g, comp, xb, fb, dv)
-    vz = I.node_volumes_z(g, comp)
+    vz = _volumes_z(g, comp)
     lhs = (dv * fb * I.interpolate(u, g, comp, xb)).sum()
     rhs = (f * u * (g.dx * g.dy * vz[:, None, None])).sum()
     assert abs(lhs - rhs) < 1e-13 * (np.abs(dv * fb).sum() * np.abs(u).max())
+
+
+@pytest.mark.parametrize("comp", [0, 1, 2])
+def test_linear_field_on_the_staggered_positions(comp):
+    """A linear function sampled where the staggered grid stores component
+    comp (u on x faces i dx, v on y faces j dy, w on z faces zc[k], cell
+    centres along the other axes; positions written out here, not taken from
+    the oracle) is reproduced exactly at any marker: pins the node positions."""
+    g = grid((WALL, WALL))
+    zc = g.zc
+    xs = np.arange(g.nx) * g.dx + (0.0 if comp == 0 else 0.5 * g.dx)
+    ys = np.arange(g.ny) * g.dy + (0.0 if comp == 1 else 0.5 * g.dy)
+    zs = zc[:-1] if comp == 2 else 0.5 * (zc[1:] + zc[:-1])
+    a, bx, by, bz = 0.4, 1.3, -0.6, 2.1
+    field = a + bx * xs[None, None, :] + by * ys[None, :, None] + bz * zs[:, None, None]
+    xb = markers(g, 80, 60 + comp)
+    got = I.interpolate(field, g, comp, xb)
+    exact = a + bx * xb[:, 0] + by * xb[:, 1] + bz * xb[:, 2]
+    np.testing.assert_allclose(got, exact, rtol=0, atol=1e-12 * np.abs(exact).max())
