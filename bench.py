@@ -429,6 +429,61 @@ def cpu_baseline_viscous(spec, beta):
             "seconds_for_sample": round(t_all, 3)}
 
 
+def cpu_baseline_momentum(spec, planes=16):
+    """The FP64 CPU oracle of the momentum right-hand side, timed on a slab of
+    `planes` z-planes of the same grid (every plane costs the same), scaled by
+    nz / planes (steps/s of the whole grid)."""
+    import numpy as np
+    import oracle
+    from oracle import momentum as MO
+    from paper_2103_15187_amd import workloads as W
+    zc = spec.zc()
+    lo = spec.nz // 2 - planes // 2
+    g = oracle.Grid(spec.nx, spec.ny, planes, spec.bcx, spec.bcy, spec.dx, spec.dy, zc[lo:lo + planes + 1])
+    r = W.rng(11)
+    shape = (planes, spec.ny, spec.nx)
+    u, v, w = (r.standard_normal(shape) for _ in range(3))
+    prev = tuple(r.standard_normal(shape) for _ in range(3))
+    t0 = time.perf_counter()
+    MO.momentum_rhs(u, v, w, prev, g, dt=1e-3, re=300.0)
+    dt = time.perf_counter() - t0
+    total = dt * spec.nz / planes
+    return {"value": round(1.0 / total, 6), "unit": "steps/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle", "sample": f"oracle right-hand side of {planes} of {spec.nz} z-planes "
+            f"({spec.nx}x{spec.ny}x{planes}, same spacing), {dt:.2f} s, scaled by {spec.nz / planes:g}",
+            "seconds_for_sample": round(dt, 3)}
+
+
+def cpu_baseline_ib(spec, planes=24, max_markers=1500):
+    """The FP64 CPU oracle of the IB-MLS step (interpolation of u, v, w and
+    spreading of one value per marker and component), timed on the surface
+    markers of a slab of z-planes (markers two planes or more from the slab's
+    ends, so their supports are those of the whole grid), scaled by the
+    marker count (steps/s for all markers)."""
+    import numpy as np
+    import oracle
+    from oracle import ibm as IB
+    from paper_2103_15187_amd import workloads as W
+    xb, dv = W.spheroid_markers(spec)
+    zc = spec.zc()
+    lo = spec.nz // 2 - planes // 2
+    sel = np.nonzero((xb[:, 2] > zc[lo + 3]) & (xb[:, 2] < zc[lo + planes - 3]))[0][:max_markers]
+    g = oracle.Grid(spec.nx, spec.ny, planes, spec.bcx, spec.bcy, spec.dx, spec.dy, zc[lo:lo + planes + 1])
+    r = W.rng(12)
+    field = r.standard_normal((planes, spec.ny, spec.nx))
+    fb = r.standard_normal(len(sel))
+    t0 = time.perf_counter()
+    for comp in range(3):
+        IB.interpolate(field, g, comp, xb[sel])
+        IB.spread(g, comp, xb[sel], fb, dv[sel])
+    dt = time.perf_counter() - t0
+    total = dt * len(xb) / len(sel)
+    return {"value": round(1.0 / total, 6), "unit": "steps/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle", "sample": f"oracle transfer of {len(sel)} of the {len(xb)} surface markers (those "
+            f"in a {planes}-plane slab, on that slab's grid), {dt:.2f} s, scaled by the marker count",
+            "seconds_for_sample": round(dt, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,10 +587,16 @@ def main():
         ms.pop("max_abs_div_after", None)
         ms["steps_per_s"] = ms.pop("solves_per_s")
         ms["roofline"] = roofline_for("momentum_fp64", mres, ncells)
+        if not args.no_cpu_baseline:
+            ms["cpu_baseline"] = cpu_baseline_momentum(spec)
         line["modes"]["momentum_fp64"] = ms
-        log("[bench] IB-MLS transfer of 10^6 markers")
-        line["modes"]["ib_mls_fp64"] = gpu_ib(spec, u0, args.steps, args.warmup, torch, fsei)
-        log(f"[bench] IB-MLS: {line['modes']['ib_mls_fp64']['ms_per_step']:.3f} ms/step")
+        log("[bench] IB-MLS transfer of ~10^6 surface markers")
+        ib = gpu_ib(spec, u0, args.steps, args.warmup, torch, fsei)
+        ib["steps_per_s"] = round(1e3 / ib["ms_per_step"], 2)
+        if not args.no_cpu_baseline:
+            ib["cpu_baseline"] = cpu_baseline_ib(spec)
+        line["modes"]["ib_mls_fp64"] = ib
+        log(f"[bench] IB-MLS: {ib['ms_per_step']:.3f} ms/step")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a bounded sample)")
         line["cpu_baseline"] = cpu_baseline(spec)
