@@ -157,3 +157,33 @@ def test_c3_ib_surface_markers_transpose_and_sampled_parity():
             flat, phi = IB.shape_functions(g, comp, xb[b])
             ref = phi @ uh[flat]
             assert abs(iuh[b] - ref) <= 1e-12 * np.abs(uh[flat]).max(), (comp, b)
+
+
+@pytest.mark.parametrize("case", ["uniform_overflow", "one_cell_cluster"])
+def test_ib_spread_combining_edge_cases(case):
+    """Spreading combines a workgroup's adds in a table of 4096 nodes before
+    the global atomics.  uniform_overflow: 2560 uniform markers on 64^3 cells
+    (a workgroup's 6912 adds land on more distinct nodes than the table holds,
+    so part of them take the direct path); one_cell_cluster: 1000 markers
+    inside one cell (every add of a workgroup lands on a few dozen nodes).
+    Both element by element against the oracle."""
+    spec = W.GridSpec(64, 64, 64, PERIODIC, WALL, 1.0, 1.0, 1.0, 1.5)
+    g = oracle.Grid(spec.nx, spec.ny, spec.nz, spec.bcx, spec.bcy, spec.dx, spec.dy, spec.zc())
+    F = fsei()
+    plan = F.Plan.from_spec(spec)
+    r = W.rng(70)
+    if case == "uniform_overflow":
+        xb = markers(spec, 2560, 71)
+    else:
+        c0 = np.array([0.3 * spec.lx, 0.6 * spec.ly, 0.5 * spec.lz])
+        xb = c0 + r.uniform(-0.4, 0.4, (1000, 3)) * np.array([spec.dx, spec.dy, spec.dx])
+    nb = len(xb)
+    fb = r.standard_normal(nb)
+    dvb = r.uniform(0.5, 1.5, nb) * spec.dx * spec.dy * 1e-2
+    for comp in range(3):
+        print(f"ib spread {case} comp={comp}", flush=True)
+        fd = torch.zeros(spec.shape, dtype=torch.float64, device="cuda")
+        plan.ib_spread(fd, comp, dev(xb), dev(fb), dev(dvb))
+        torch.cuda.synchronize()
+        sref = IB.spread(g, comp, xb, fb, dvb)
+        assert np.abs(host(fd) - sref).max() <= 1e-12 * np.abs(sref).max(), (case, comp)
