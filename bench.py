@@ -11,7 +11,7 @@ the timed region.  Both precision modes are measured in the same run:
                   (the mode this workload is specified with; reported as value)
   * fp64        : every step in FP64
 
-Prints ONE JSON line.  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  `--gpus N` with N > 1 exits: the path runs on one GPU.
 """
 from __future__ import annotations
 
@@ -513,7 +513,7 @@ def main():
             "python3 bench.py --summarize gpurun_out")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs the projection on one GPU only; multi-GPU runs are not supported "
+        print("bench.py: the projection runs on one GPU only; multi-GPU runs are not supported "
               "(the slab decomposition is a design note, not built)", file=sys.stderr)
         sys.exit(2)
     if args.steps + args.warmup > 30:
