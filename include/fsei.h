@@ -177,7 +177,9 @@ fsei_status fsei_viscous_solve(fsei_plan* plan, int component, double* q, double
 /* As fsei_viscous_solve, with the increment added to the velocity in the
  * same pass: u <- u + dq (the provisional velocity u* = u^n + du of the
  * fractional step).  rhs is used as scratch (its contents on return are the
- * x and y stages' intermediate, not dq); u must not alias rhs. */
+ * x and y stages' intermediate, not dq); u must not alias rhs.  dq is 0 on
+ * dead wall faces, so those entries of u keep whatever they held (the
+ * projection ignores them on input and writes them 0). */
 fsei_status fsei_viscous_solve_add(fsei_plan* plan, int component, double* rhs, double* u, double beta);
 
 /* Explicit right-hand side of the momentum step (paper, Sec. 2.1, eq.
