@@ -220,6 +220,10 @@ void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add3
 template <typename T, int EMAX, int NTHR>
 void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     a.nseq = std::max(1, std::min(tile_nseq(EMAX, p->ny), (p->nx + 1) / 2));
+    // whole 128-byte row segments per tile where the tile holds at least one
+    // (16 doubles / 32 floats = 8 / 16 column pairs)
+    constexpr int kSeqLine = 64 / (int)sizeof(T);
+    if (a.nseq > kSeqLine) a.nseq -= a.nseq % kSeqLine;
     const int tx = 2 * a.nseq;
     a.ntile = (p->nx + tx - 1) / tx;
     const unsigned nb = (unsigned)(a.ntile * p->nz);
@@ -277,10 +281,8 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
         launch_y_cfg<T, 2048, 256>(p, a, inverse);
     else if (want <= 4096 || !fits(8192))
         launch_y_cfg<T, 4096, 512>(p, a, inverse);
-    else if (sizeof(T) == 8 || want <= 8192 || !fits(16384))
-        launch_y_cfg<T, 8192, 1024>(p, a, inverse);
     else
-        launch_y_cfg<T, (sizeof(T) == 8 ? 8192 : 16384), 1024>(p, a, inverse);
+        launch_y_cfg<T, 8192, 1024>(p, a, inverse);
 }
 
 // Tiling of the z solve: 0 = adjacent modes per lane as one vector: two
