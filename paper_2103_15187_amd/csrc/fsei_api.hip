@@ -403,19 +403,25 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
         a.sigma_thr = (float)p->sigma_thr;
         int L, P;
-        if (zcfg() == 0 && p->nx % 4 == 0 && choose_chunks(nz, 32, &L, &P)) {
+        int cfg = zcfg();
+        // 32 chunks of 32 rows (nz > 768) spill registers in the default
+        // tiling; 64 chunks of at most 16 rows with two modes per lane do
+        // not.  FP32 solves only: in FP64 that tiling left an 8x larger
+        // residual at 768 x 768 x 1024 (6.2e-9 -> 4.9e-8), so FP64 keeps 32.
+        if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P) && L > 24) cfg = 3;
+        if (cfg == 0 && p->nx % 4 == 0 && choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
             zv_dispatch<float, float, 4, 16, 512>(p, a, dim3((p->nx / 4 + 15) / 16, p->ny));
-        } else if ((zcfg() == 0 || zcfg() == 4) && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+        } else if ((cfg == 0 || cfg == 4) && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
             zv_dispatch<float, float, 2, 32, 1024>(p, a, dim3((p->nx / 2 + 31) / 32, p->ny));
-        } else if (zcfg() == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
+        } else if (cfg == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
             zv_dispatch<float, float, 2, 16, 1024>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
-        } else if (zcfg() == 1 && choose_chunks(nz, 64, &L, &P)) {
+        } else if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
             z_dispatch<float, float, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);

@@ -339,3 +339,34 @@ def test_refine_projection_generic_tiling(dims, bc):
     assert info["rel_residual"] <= 1e-10
     assert oracle.rel_residual(oracle.divergence(u, v, w, g), gp, g) <= 1e-10
     assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
+
+
+def test_long_z_lines_adjoint_fp32_and_refine():
+    """nz = 1000: FP32 solves take the z tiling of 64 chunks of 16 rows (32
+    chunks of 32 rows would spill registers), FP64 keeps 32 chunks: the FP32
+    projection, FP32+refine and the FP64 adjoint (transposed tridiagonal)
+    against the oracle."""
+    F = fsei()
+    spec = W.small_spec(32, 16, 1000, PERIODIC, WALL, lx=4.0, ly=4.0, lz=6.5, stretch=3.0)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 31)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, _ = run_project(spec, u, v, w, precision=F.PREC_FP32)
+    print("nz=1000 fp32 errs", [rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))])
+    assert max(rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))) <= 1e-3   # a wrong tiling is O(1)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-9, max_iter=6)
+    print("nz=1000 refine", info)
+    assert info["rel_residual"] <= 1e-9
+    assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-8
+    r = W.rng(32)
+    au, av, aw = (r.standard_normal(spec.shape) for _ in range(3))
+    for a, m in zip((au, av, aw), W.dead_face_masks(spec)):
+        a[m] = 0
+    ref = oracle.project_adjoint(au, av, aw, None, g, dt=0.6)
+    plan = F.Plan.from_spec(spec)
+    da, db, dc = dev(au), dev(av), dev(aw)
+    plan.project_backward(da, db, dc, dt=0.6)
+    torch.cuda.synchronize()
+    errs = [rel(host(t), x) for t, x in zip((da, db, dc), ref)]
+    print("nz=1000 adjoint errs", errs)
+    assert max(errs) <= 1e-12
