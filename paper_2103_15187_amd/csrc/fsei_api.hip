@@ -371,7 +371,10 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         ZArgs<double, double> a = zargs<double, double>(p, data, transposed);
         a.sigma_thr = 0.0;
         int L, P;
-        const int cfg = zcfg();
+        int cfg = zcfg();
+        // 32 chunks of 32 rows (nz > 768) spill registers with two modes per
+        // lane; one mode per lane (same chunks, same arithmetic) does not
+        if (cfg == 0 && choose_chunks(nz, 32, &L, &P) && L > 24) cfg = 5;
         if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
             a.L = L;
             a.P = P;
@@ -406,8 +409,8 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         int cfg = zcfg();
         // 32 chunks of 32 rows (nz > 768) spill registers in the default
         // tiling; 64 chunks of at most 16 rows with two modes per lane do
-        // not.  FP32 solves only: in FP64 that tiling left an 8x larger
-        // residual at 768 x 768 x 1024 (6.2e-9 -> 4.9e-8), so FP64 keeps 32.
+        // not.  (In FP64 the 64-chunk tiling left an 8x larger residual at
+        // 768 x 768 x 1024, 6.2e-9 -> 4.9e-8, so FP64 keeps 32 chunks.)
         if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P) && L > 24) cfg = 3;
         if (cfg == 0 && p->nx % 4 == 0 && choose_chunks(nz, 32, &L, &P)) {
             a.L = L;

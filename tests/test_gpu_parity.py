@@ -342,10 +342,10 @@ def test_refine_projection_generic_tiling(dims, bc):
 
 
 def test_long_z_lines_adjoint_fp32_and_refine():
-    """nz = 1000: FP32 solves take the z tiling of 64 chunks of 16 rows (32
-    chunks of 32 rows would spill registers), FP64 keeps 32 chunks: the FP32
-    projection, FP32+refine and the FP64 adjoint (transposed tridiagonal)
-    against the oracle."""
+    """nz = 1000: FP32 solves take the z tiling of 64 chunks of 16 rows, FP64
+    ones 32 chunks of 32 rows with one mode per lane (two modes per lane
+    would spill registers): the FP32 projection, FP32+refine and the FP64
+    adjoint (transposed tridiagonal) against the oracle."""
     F = fsei()
     spec = W.small_spec(32, 16, 1000, PERIODIC, WALL, lx=4.0, ly=4.0, lz=6.5, stretch=3.0)
     g = grid_of(spec)
