@@ -256,10 +256,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(mode, slot):
+def measured_traffic(mode, slot, ncells):
     """Calibrated HBM bytes per launch of the slot's kernel from the committed
-    counter summary, or None when there is none for it or the sources have
-    changed since the counters were taken."""
+    counter summary, or None when there is none for it, the sources have
+    changed since the counters were taken, or the run is not the profiled
+    512x512x768 workload."""
+    from paper_2103_15187_amd import workloads as W
+    if ncells != W.CONFIGS["C3"].ncells:
+        return None
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -282,7 +286,7 @@ def roofline_for(mode, res, ncells):
     bytes_per_launch = bpc[name] * ncells
     achieved = bytes_per_launch / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mode, name),
+            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mode, name, ncells),
             "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
 
 
