@@ -22,6 +22,8 @@ def _run_pins():
         lambda: pins.test_solve_matches_bordered_dense_lu((WALL, WALL), (3, 2, 5)),
         lambda: pins.test_projection_invariants((WALL, PERIODIC)),
         lambda: pins.test_adjoint_is_dense_transpose((PERIODIC, WALL)),
+        lambda: pins.test_z_coefficients_exact_on_the_workload_grids("C3"),
+        lambda: pins.test_rel_residual_matches_dense_definition((WALL, WALL)),
     ]
     failed = 0
     for c in checks:
@@ -88,9 +90,24 @@ def _mut_adjoint_no_weights(gu, gv, gw, gp, g, dt=1.0):
     return pu, pv, pw
 
 
+def _mut_h_from_midpoints(self, dtype=np.float64):
+    zc = self.zc.astype(dtype)
+    zm = (zc[1:] + zc[:-1]) / 2
+    h = np.empty(self.nz, dtype=dtype)
+    h[0] = np.nan
+    h[1:] = np.diff(zm)
+    return np.diff(zc), h
+
+
+def _mut_residual_plain_mean(f, p, g):
+    fc = f - f.mean()
+    r = fc - O.laplacian(p, g)
+    return float(np.linalg.norm(r) / np.linalg.norm(fc))
+
+
 ORIG = {name: getattr(O, name) for name in
         ("divergence", "gradient", "eigenvalues", "z_coefficients", "thomas",
-         "zero_mode_solve", "transform_matrix", "project_adjoint")}
+         "zero_mode_solve", "transform_matrix", "project_adjoint", "rel_residual")}
 
 MUTANTS = {
     "divergence z metric uses h": ("divergence", _mut_div_uses_h),
@@ -102,14 +119,19 @@ MUTANTS = {
     "DCT-II without the half-cell shift": ("transform_matrix", _mut_dct_no_half),
     "transform matrix transposed": ("transform_matrix", _mut_transform_transposed),
     "adjoint without metric weights": ("project_adjoint", _mut_adjoint_no_weights),
+    "h as the difference of rounded midpoints": ("Grid.z_metrics", _mut_h_from_midpoints),
+    "residual centred by the plain mean": ("rel_residual", _mut_residual_plain_mean),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_is_caught(name, monkeypatch):
     attr, fn = MUTANTS[name]
-    monkeypatch.setattr(O, attr, fn)
-    if hasattr(oracle, attr):
-        monkeypatch.setattr(oracle, attr, fn)
+    if attr.startswith("Grid."):
+        monkeypatch.setattr(O.Grid, attr.split(".")[1], fn)
+    else:
+        monkeypatch.setattr(O, attr, fn)
+        if hasattr(oracle, attr):
+            monkeypatch.setattr(oracle, attr, fn)
     with np.errstate(all="ignore"):
         assert _run_pins() >= 1, f"no pin caught the mutant: {name}"

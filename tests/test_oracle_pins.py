@@ -142,6 +142,55 @@ def test_laplacian_matches_flux_assembly(bc):
     np.testing.assert_allclose(oracle.laplacian(p, g).ravel(), L @ p.ravel(), rtol=1e-13, atol=1e-10)
 
 
+@pytest.mark.parametrize("cfg", ["C3", "C5"])
+def test_z_coefficients_exact_on_the_workload_grids(cfg):
+    """The face coordinates of the tanh-stretched workload grids are binary
+    fractions, so Fractions give the exact metric: dz_k = zc_{k+1} - zc_k,
+    zm_k = (zc_k + zc_{k+1}) / 2, h_k = zm_k - zm_{k-1}, a_k = 1/(dz_k h_k),
+    c_k = 1/(dz_k h_{k+1}) (finite-volume definition, Appendix-style
+    loops).  The oracle's FP64 coefficients must be within a few rounding
+    steps of these (four operations: 4 ulp)."""
+    s = W.CONFIGS[cfg]
+    zc = s.zc()
+    g = Grid(4, 4, s.nz, WALL, WALL, 1.0, 1.0, zc)
+    a, c = oracle.z_coefficients(g)
+    zf = [Fraction(float(z)) for z in zc]
+    dz = [zf[k + 1] - zf[k] for k in range(s.nz)]
+    zm = [(zf[k] + zf[k + 1]) / 2 for k in range(s.nz)]
+    ulp = np.finfo(np.float64).eps
+    worst = 0.0
+    for k in range(s.nz):
+        ea = 1 / (dz[k] * (zm[k] - zm[k - 1])) if k >= 1 else Fraction(0)
+        ec = 1 / (dz[k] * (zm[k + 1] - zm[k])) if k + 1 < s.nz else Fraction(0)
+        for got, ex in ((a[k], ea), (c[k], ec)):
+            if ex == 0:
+                assert got == 0.0
+            else:
+                worst = max(worst, abs(float((Fraction(float(got)) - ex) / ex)))
+    assert worst <= 4 * ulp, worst
+
+
+@pytest.mark.parametrize("bc", [(WALL, WALL), (PERIODIC, WALL)])
+def test_rel_residual_matches_dense_definition(bc):
+    """rel_residual = ||(f - mean_V f) - L p|| / ||f - mean_V f|| with L the
+    loop-built flux assembly and the volume-weighted mean of the brute-force
+    cell volumes (stretched z: the plain mean differs)."""
+    s = W.small_spec(5, 4, 7, bc[0], bc[1], lx=1.3, ly=0.8, lz=2.0, stretch=2.5)
+    g = grid_of(s)
+    r = W.rng(41)
+    f = r.standard_normal(s.shape) + 0.3
+    p = r.standard_normal(s.shape)
+    L = bf.dense_laplacian(s.nx, s.ny, s.nz, s.bcx, s.bcy, s.dx, s.dy, s.zc())
+    V = bf.cell_volumes(s.nx, s.ny, s.nz, s.dx, s.dy, s.zc())
+    fc = f.ravel() - (V * f.ravel()).sum() / V.sum()
+    ref = np.linalg.norm(fc - L @ p.ravel()) / np.linalg.norm(fc)
+    got = oracle.rel_residual(f, p, g)
+    assert abs(got - ref) <= 1e-13 * ref
+    # the exact solution has (rounding-level) zero residual
+    ps = oracle.poisson_solve(f, g)
+    assert oracle.rel_residual(f, ps, g) < 1e-13
+
+
 # --------------------------------------------------------------------------
 # the solve: brute force on tiny grids, exact arithmetic, iterative solver
 # --------------------------------------------------------------------------
