@@ -6,10 +6,17 @@ velocity field that is already resident in HBM.  Each timed step projects its
 own copy of the input (the projection works in place), so no copy runs inside
 the timed region.  Both precision modes are measured in the same run:
 
-  * fp32_refine : FP32 transforms/tridiagonals (lowest-mode lines in FP64),
-                  FP64 residual, correction solves to ||r||/||f|| <= 1e-10
+  * fp32_refine : FP32 transforms/tridiagonals (near-singular mode lines in
+                  FP64), FP64 residual, correction solves to ||r||/||f|| <= 1e-10
                   (the mode this workload is specified with; reported as value)
   * fp64        : every step in FP64
+
+Beside the projection the line carries: the Poisson solve on the 768 x 768 x
+1024 grid (power-law right-hand side, FP32+refine and FP64; not in value),
+the error of both modes against the FP64 oracle on a 96-plane slab of the
+512 x 512 x 768 grid, the bandwidth of a plain copy kernel as a second
+denominator, and the legs of the fractional step around the projection
+(viscous step, momentum right-hand side, IB-MLS transfer).
 
 Prints ONE JSON line.  `--gpus N` with N > 1 exits: the path runs on one GPU.
 """
@@ -35,7 +42,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_512x512x768.json")
 SLOT_KERNEL = {
     "fp64": {"xfwd": "k_xfwd<double, double, 1, 2048, 256, 512>", "yfwd": "k_yfwd<double, 4096, 512, 512, 4>",
              "zsolve": "k_zsolvev<double, double, 2, 16, 24, 512>", "yinv": "k_yinv<double, 4096, 512, 512, 4>",
-             "xinv": "k_xinv<double, double, 0, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256, 16>"},
+             "xinv": "k_xinv<double, double, 0, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256, 16>",
+             "xinv_grad": "k_xinv_grad<512>"},
     "fp32_refine": {"xfwd": "k_xfwd<double, float, 1, 2048, 256, 512>", "yfwd": "k_yfwd<float, 8192, 1024, 512, 6>",
                     "zsolve": "k_zsolvev<float, float, 4, 16, 24, 512>", "yinv": "k_yinv<float, 8192, 1024, 512, 4>",
                     "xinv": "k_xinv<float, float, 0, 2048, 256, 512>", "xinv_acc": "k_xinv<float, double, 2, 2048, 256, 512>",
@@ -51,7 +59,7 @@ SLOT_KERNEL = {
 # Algorithmic HBM bytes per cell of each kernel launch (minimum pass model:
 # every operand read once, every result written once).
 BYTES_PER_CELL = {
-    "fp64": {"xfwd": 32, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "grad": 56},
+    "fp64": {"xfwd": 32, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16, "grad": 56, "xinv_grad": 64},
     # refinement at this workload (pair tiling): the first solve's pressure is
     # FP32 (x inverse writes 4 B; the first residual reads it: f 8 + p 4, r 4
     # written; the first correction reads p32 + delta and writes p 8)
@@ -59,14 +67,57 @@ BYTES_PER_CELL = {
                     "resid": 16, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 16, "grad": 56, "grad_resid": 64},
     # implicit viscous step: every line solve of one component reads and
     # writes the field once (3 components x 3 directions = 144 B/cell)
+    # Poisson solves (f read, p written): FP64 and FP32+refine (FP64 input,
+    # an FP64 copy of f kept for the residual)
+    "solve_fp64": {"xfwd": 16, "yfwd": 16, "zsolve": 16, "yinv": 16, "xinv": 16},
+    "solve_fp32_refine": {"xfwd": 20, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 8, "resid": 16, "xfwd_r": 8,
+                          "resid_norm": 16, "xinv_acc": 16},
     "viscous_fp64": {"visc_x": 16, "visc_y": 16, "visc_z": 16},
     # explicit momentum right-hand side: u, v, w and N^{n-1} read, rhs and N^n written
     "momentum_fp64": {"momentum_rhs": 96},
 }
 
 
+# Minimum-pass model of a whole step (bytes per cell; every field crossing HBM
+# once per pass the method needs): the FP64 projection 144 (divergence + x
+# transform 32, y 16, z 16, y inverse 16, x inverse + gradient 64); the
+# FP32+refine projection with FP64 input and output 72 for the first solve
+# (including storing f in FP64), 64 per correction beyond the last, and 64 for
+# the last correction fused with the gradient and the convergence check
+# (136 + 64 k for k corrections); the Poisson solves 80 (FP64) and 48 + 64 k +
+# 16 (FP32+refine).
+def model_bytes_per_cell(mode, iterations):
+    k = max(int(iterations or 0), 1)
+    return {"fp64": 144, "fp32_refine": 136 + 64 * k, "solve_fp64": 80,
+            "solve_fp32_refine": 64 + 64 * k}.get(mode)
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(step, steps, warmup, plan, torch):
+    """Run `warmup` untimed then `steps` timed calls of step(i); the library
+    records HIP events around every launch on the plan's stream during the
+    timed region (per-kernel times), and an event pair on the same stream
+    brackets every step (median step time).  Returns (wall ms per step,
+    median event ms per step, kernel times)."""
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    plan.reset_timing()
+    plan.set_timing(True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        ev[i][0].record()
+        step(warmup + i)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    plan.set_timing(False)
+    med = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    return (t1 - t0) * 1e3 / steps, med, plan.kernel_times()
 
 
 def gpu_mode(mode, spec, u0, v0, w0, steps, warmup, torch, fsei):
@@ -78,44 +129,66 @@ def gpu_mode(mode, spec, u0, v0, w0, steps, warmup, torch, fsei):
     p = torch.empty_like(u0)
     torch.cuda.synchronize()
     infos = []
-    for i in range(warmup):
-        _, info = plan.project(*bufs[i], p=p, info=True)
-        infos.append(info)
-    torch.cuda.synchronize()
-    # refine mode reads one residual norm per iteration back to the host;
-    # FP64 mode runs without any host synchronisation inside the loop
-    t0 = time.perf_counter()
-    for i in range(warmup, ncopy):
+
+    def step(i):
+        # refine mode reads one residual norm per iteration back to the host;
+        # FP64 mode runs without any host synchronisation
         if mode == "fp64":
             plan.project(*bufs[i], p=p)
         else:
-            _, info = plan.project(*bufs[i], p=p, info=True)
-            infos.append(info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # per-kernel times from HIP events the library records around every
-    # launch, in a separate instrumented pass over fresh copies of the input
-    # (the events are kept out of the timed loop above)
-    nk = min(steps, 3)
-    for i in range(nk):
-        for dst, src in zip(bufs[i], (u0, v0, w0)):
-            dst.copy_(src)
-    torch.cuda.synchronize()
-    plan.reset_timing()
-    plan.set_timing(True)
-    for i in range(nk):
-        plan.project(*bufs[i], p=p)
-    torch.cuda.synchronize()
-    plan.set_timing(False)
-    ktimes = plan.kernel_times()
-    # check the last output: divergence of the projected field, V-mean of p
-    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": ktimes, "kernel_steps": nk}
+            infos.append(plan.project(*bufs[i], p=p, info=True)[1])
+    ms, med, ktimes = timed_steps(step, steps, warmup, plan, torch)
+    res = {"ms_per_step": ms, "median_step_ms": med, "kernels": ktimes, "kernel_steps": steps}
     res["last_info"] = infos[-1] if infos else None
+    # check the last output: divergence of the projected field
     u, v, w = bufs[-1]
     res["div_check"] = float(divergence_max(u, v, w, spec, torch))
     del bufs
     torch.cuda.empty_cache()
     return res, plan
+
+
+def gpu_solve(mode, spec, f0, steps, warmup, torch, fsei):
+    """Time `steps` Poisson solves p = L^+ f of a resident right-hand side
+    (the solve reads f and writes p; f is not modified)."""
+    prec = fsei.PREC_FP64 if mode == "solve_fp64" else fsei.PREC_FP32_REFINE
+    plan = fsei.Plan.from_spec(spec, precision=prec, rtol=1e-10, max_iter=6, accept_floor=True)
+    p = torch.empty_like(f0)
+    infos = []
+
+    def step(i):
+        if mode == "solve_fp64":
+            plan.poisson_solve(f0, p)
+        else:
+            infos.append(plan.poisson_solve(f0, p, info=True)[1])
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", RuntimeWarning)   # refinement stopping at the FP64 floor
+        ms, med, ktimes = timed_steps(step, steps, warmup, plan, torch)
+    res = {"ms_per_step": ms, "median_step_ms": med, "kernels": ktimes, "kernel_steps": steps,
+           "last_info": infos[-1] if infos else None, "div_check": None}
+    del p
+    torch.cuda.empty_cache()
+    return res
+
+
+def copy_bandwidth(field, torch, reps=10):
+    """GB/s of a plain device copy of one FP64 field (8 B read + 8 B written
+    per cell), median of `reps` copies timed with events: the streaming
+    ceiling the kernels are also compared with."""
+    dst = torch.empty_like(field)
+    dst.copy_(field)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(field)
+        b.record()
+        torch.cuda.synchronize()
+        t.append(a.elapsed_time(b))
+    del dst
+    return 2.0 * field.numel() * field.element_size() / (float(np.median(t)) / 1e3) / 1e9
 
 
 def gpu_viscous(spec, u0, v0, w0, steps, warmup, torch, fsei):
@@ -125,22 +198,8 @@ def gpu_viscous(spec, u0, v0, w0, steps, warmup, torch, fsei):
     plan = fsei.Plan.from_spec(spec)
     beta = 0.5 * spec.dx ** 2
     u, v, w = u0.clone(), v0.clone(), w0.clone()
-    for _ in range(warmup):
-        plan.viscous_step(u, v, w, beta)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.viscous_step(u, v, w, beta)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    nk = min(steps, 3)
-    plan.reset_timing()
-    plan.set_timing(True)
-    for _ in range(nk):
-        plan.viscous_step(u, v, w, beta)
-    torch.cuda.synchronize()
-    plan.set_timing(False)
-    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": plan.kernel_times(), "kernel_steps": nk,
+    ms, med, kt = timed_steps(lambda i: plan.viscous_step(u, v, w, beta), steps, warmup, plan, torch)
+    res = {"ms_per_step": ms, "median_step_ms": med, "kernels": kt, "kernel_steps": steps,
            "last_info": None, "div_check": None, "beta": beta}
     del u, v, w
     torch.cuda.empty_cache()
@@ -154,22 +213,8 @@ def gpu_momentum(spec, u0, v0, w0, steps, warmup, torch, fsei):
     n = [torch.zeros_like(u0) for _ in range(3)]
     r = [torch.empty_like(u0) for _ in range(3)]
     dt, re = 1e-3, 1000.0
-    for _ in range(warmup):
-        plan.momentum_rhs(u0, v0, w0, n, r, dt, re)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.momentum_rhs(u0, v0, w0, n, r, dt, re)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    nk = min(steps, 3)
-    plan.reset_timing()
-    plan.set_timing(True)
-    for _ in range(nk):
-        plan.momentum_rhs(u0, v0, w0, n, r, dt, re)
-    torch.cuda.synchronize()
-    plan.set_timing(False)
-    res = {"ms_per_step": (t1 - t0) * 1e3 / steps, "kernels": plan.kernel_times(), "kernel_steps": nk,
+    ms, med, kt = timed_steps(lambda i: plan.momentum_rhs(u0, v0, w0, n, r, dt, re), steps, warmup, plan, torch)
+    res = {"ms_per_step": ms, "median_step_ms": med, "kernels": kt, "kernel_steps": steps,
            "last_info": None, "div_check": None}
     del n, r
     torch.cuda.empty_cache()
@@ -192,29 +237,16 @@ def gpu_ib(spec, u0, steps, warmup, torch, fsei):
     ub = torch.empty(nb, dtype=torch.float64, device=u0.device)
     f = torch.zeros_like(u0)
 
-    def step():
+    def step(i):
         for c in range(3):
             plan.ib_interpolate(u0, c, xd, ub)
             plan.ib_spread(f, c, xd, fb, dvb)
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plan.reset_timing()
-    plan.set_timing(True)
-    step()
-    torch.cuda.synchronize()
-    plan.set_timing(False)
-    kt = plan.kernel_times()
-    ms = (t1 - t0) * 1e3 / steps
+    ms, med, kt = timed_steps(step, steps, warmup, plan, torch)
     del f, xd, fb, dvb, ub
     torch.cuda.empty_cache()
-    return {"ms_per_step": round(ms, 4), "markers": nb, "markers_per_s": round(nb / (ms / 1e3), 1),
-            "kernel_ms_per_step": {k: round(v[0], 4) for k, v in kt.items()},
+    return {"ms_per_step": round(ms, 4), "median_step_ms": round(med, 4), "markers": nb,
+            "markers_per_s": round(nb / (ms / 1e3), 1),
+            "kernel_ms_per_step": {k: round(v[0] / steps, 4) for k, v in kt.items()},
             "note": "one step = interpolation of u, v, w at every marker + spreading of one value per marker "
                     "and component (27-node MLS supports, FP64 atomics); markers: triangle centroids of a prolate "
                     "spheroid (semi-axes 1.2, 1.2, 2.4) centred in the 512x512x768 domain, mesh order"}
@@ -275,9 +307,10 @@ def measured_traffic(mode, slot, ncells):
     return None if k is None else round(k["fetch_bytes"] + k["write_bytes"])
 
 
-def roofline_for(mode, res, ncells):
-    """Dominant kernel (largest total time) and its achieved algorithmic
-    bandwidth over the timed region."""
+def roofline_for(mode, res, ncells, copy_gbs=None):
+    """Dominant kernel (largest total time in the timed region) and its
+    achieved algorithmic bandwidth: algorithmic bytes per launch over its
+    average launch duration (HIP events on the plan's stream)."""
     kt = res["kernels"]
     bpc = BYTES_PER_CELL[mode]
     name = max((k for k in kt if k in bpc), key=lambda k: kt[k][0])
@@ -285,9 +318,13 @@ def roofline_for(mode, res, ncells):
     avg_s = total_ms / n / 1e3
     bytes_per_launch = bpc[name] * ncells
     achieved = bytes_per_launch / avg_s / 1e9
-    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mode, name, ncells),
-            "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    out = {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+           "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(mode, name, ncells),
+           "bytes_per_launch": bytes_per_launch, "avg_launch_ms": round(avg_s * 1e3, 4)}
+    if copy_gbs:
+        out["copy_ceiling"] = round(copy_gbs, 1)
+        out["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    return out
 
 
 def _short_kernel(name):
@@ -352,25 +389,38 @@ def summarize_profiles(d, cmd_trace, cmd_pmc):
         fh.write("\n".join(md) + "\n")
 
 
-def mode_summary(mode, res, ncells):
+def mode_summary(mode, res, ncells, copy_gbs=None):
+    """Rates of one leg.  hbm_frac_of_peak prices the step at the minimum-pass
+    model of the method (model_bytes_per_cell) where there is one; the bytes
+    of the launches this build actually makes are reported beside it."""
     kt = res["kernels"]
-    bpc = BYTES_PER_CELL[mode]
+    bpc = BYTES_PER_CELL.get(mode, {})
     sec = res["ms_per_step"] / 1e3
-    # algorithmic bytes per step from the launches actually made
-    ks = res["kernel_steps"]   # steps of the instrumented pass the kernel times cover
-    bytes_step = sum(bpc.get(k, 0) * ncells * n for k, (ms, n) in kt.items()) / ks
+    ks = res["kernel_steps"]   # steps the kernel times cover
+    build_step = sum(bpc.get(k, 0) * ncells * n for k, (ms, n) in kt.items()) / ks
+    iters = res["last_info"]["iterations"] if res.get("last_info") else 0
+    mb = model_bytes_per_cell(mode, iters)
+    model_step = mb * ncells if mb else build_step
     out = {
         "solves_per_s": round(1.0 / sec, 3),
         "gpts_per_s": round(ncells / sec / 1e9, 3),
         "ms_per_step": round(res["ms_per_step"], 4),
-        "model_bytes_per_step_GB": round(bytes_step / 1e9, 3),
-        "hbm_frac_of_peak": round(bytes_step / sec / 1e9 / PEAK_HBM_GBS, 4),
+        "median_step_ms": round(res["median_step_ms"], 4),
+        "model_bytes_per_cell": mb if mb else round(build_step / ncells, 2),
+        "model_bytes_per_step_GB": round(model_step / 1e9, 3),
+        "hbm_frac_of_peak": round(model_step / sec / 1e9 / PEAK_HBM_GBS, 4),
+        "build_bytes_per_cell": round(build_step / ncells, 2),
         "kernel_ms_per_step": {k: round(ms / ks, 4) for k, (ms, n) in kt.items()},
-        "max_abs_div_after": res["div_check"],
     }
+    if copy_gbs:
+        out["frac_of_copy"] = round(model_step / sec / 1e9 / copy_gbs, 4)
+    if res.get("div_check") is not None:
+        out["max_abs_div_after"] = res["div_check"]
     if res["last_info"]:
         out["iterations"] = res["last_info"]["iterations"]
         out["rel_residual"] = res["last_info"]["rel_residual"]
+        if res["last_info"].get("floor_reached"):
+            out["floor_reached"] = True
     return out
 
 
@@ -378,7 +428,8 @@ def cpu_baseline(spec):
     """The FP64 CPU oracle, timed on a bounded sample of the same workload:
     the full projection of the bottom 96 of the 768 z-planes of the same grid
     (same x,y lengths and stretched faces, 1/8 of the cells), scaled to
-    solves/s of the whole grid."""
+    solves/s of the whole grid.  Also returns the sample and the oracle's
+    result (for the GPU's error against it)."""
     import oracle
     from paper_2103_15187_amd import workloads as W
     nzs = 96
@@ -393,13 +444,14 @@ def cpu_baseline(spec):
     except Exception:
         pass
     t0 = time.perf_counter()
-    oracle.project(u, v, w, g)
+    ref = oracle.project(u, v, w, g)
     dt = time.perf_counter() - t0
     frac = nzs / spec.nz
-    return {"value": round(frac / dt, 6), "unit": "solves/s", "cores": threads or len(os.sched_getaffinity(0)),
-            "kind": "oracle", "sample": f"full FP64 oracle projection of the bottom {nzs} of {spec.nz} z-planes "
-            f"({spec.nx}x{spec.ny}x{nzs}, same grid), {dt:.2f} s, scaled by {spec.nz // nzs}",
-            "seconds_for_sample": round(dt, 3), "host_cores": len(os.sched_getaffinity(0))}
+    cb = {"value": round(frac / dt, 6), "unit": "solves/s", "cores": threads or len(os.sched_getaffinity(0)),
+          "kind": "oracle", "sample": f"full FP64 oracle projection of the bottom {nzs} of {spec.nz} z-planes "
+          f"({spec.nx}x{spec.ny}x{nzs}, same grid), {dt:.2f} s, scaled by {spec.nz // nzs}",
+          "seconds_for_sample": round(dt, 3), "host_cores": len(os.sched_getaffinity(0))}
+    return cb, (sub, zc, (u, v, w), ref)
 
 
 def cpu_baseline_viscous(spec, beta):
@@ -488,6 +540,29 @@ def cpu_baseline_ib(spec, planes=24, max_markers=1500):
             "seconds_for_sample": round(dt, 3)}
 
 
+def err_vs_oracle(spec, oracle_out, torch, fsei):
+    """Relative L2 errors of the GPU projection (FP64 and FP32+refine, the
+    benchmark's launch configuration) against the oracle's result on the
+    cpu_baseline sample (the bottom 96 z-planes of the grid)."""
+    sub, zc, (u, v, w), ref = oracle_out
+    out = {"sample": f"bottom {sub.nz} of {spec.nz} z-planes ({sub.nx}x{sub.ny}x{sub.nz}, same grid), "
+                     f"u* N(0,1), against the FP64 oracle's projection"}
+    for mode, prec in (("fp64", fsei.PREC_FP64), ("fp32_refine", fsei.PREC_FP32_REFINE)):
+        plan = fsei.Plan(sub.nx, sub.ny, sub.nz, (sub.bcx, sub.bcy), sub.dx, sub.dy, zc, precision=prec,
+                         rtol=1e-10, max_iter=4)
+        d = [torch.from_numpy(a).cuda() for a in (u, v, w)]
+        p, info = plan.project(*d, p=torch.empty_like(d[0]), info=True)
+        torch.cuda.synchronize()
+        e = {k: float(np.linalg.norm(t.cpu().numpy() - r) / np.linalg.norm(r))
+             for k, t, r in zip("uvwp", (*d, p), ref)}
+        out[mode] = {k: float(f"{x:.3e}") for k, x in e.items()}
+        if mode == "fp32_refine":
+            out[mode]["rel_residual"] = float(f"{info['rel_residual']:.3e}")
+        del plan, d, p
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -499,6 +574,9 @@ def main():
     ap.add_argument("--no-viscous", action="store_true",
                     help="skip the implicit viscous step, the momentum right-hand side and the IB-MLS transfer "
                          "(reported beside the projection, not in value)")
+    ap.add_argument("--no-c5", action="store_true",
+                    help="skip the 768x768x1024 Poisson solves (reported beside the projection, not in value)")
+    ap.add_argument("--c5-steps", type=int, default=4)
     ap.add_argument("--calib", action="store_true",
                     help="also run torch.neg over one field (a plain streaming kernel of known size: "
                          "reads and writes 8 B per cell) to calibrate hardware byte counters")
@@ -509,11 +587,11 @@ def main():
         summarize_profiles(
             args.summarize,
             "rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o c3 --output-format csv -- "
-            "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline",
+            "python3 bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-c5",
             "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_FETCH_SIZE -o c3 --output-format csv -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib\n"
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-c5 --calib\n"
             "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_WRITE_SIZE -o c3 --output-format csv -- "
-            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --calib\n"
+            "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-c5 --calib\n"
             "python3 bench.py --summarize gpurun_out")
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -529,8 +607,10 @@ def main():
     log(f"[bench] generating {args.config} input {spec.shape}")
     if args.config == "C3":
         u, v, w = W.c3_velocity(spec, W.SEEDS["C3"])
+        recipe = "u* N(0,1) + Gaussian jet (amplitude 10, width 0.05 Lx)"
     else:
         u, v, w = W.random_velocity(spec, W.SEEDS.get(args.config, 1))
+        recipe = "u* N(0,1)"
     dev = torch.device("cuda:0")
     u0, v0, w0 = (torch.from_numpy(a).to(dev) for a in (u, v, w))
     del u, v, w
@@ -540,17 +620,20 @@ def main():
         torch.neg(u0, out=tmp)
         torch.cuda.synchronize()
         del tmp
+    copy_gbs = copy_bandwidth(u0, torch)
+    log(f"[bench] plain copy of one field: {copy_gbs:.0f} GB/s")
     modes = [m for m in args.modes.split(",") if m]
     results = {}
     for m in modes:
         log(f"[bench] mode {m}: warmup {args.warmup}, steps {args.steps}")
         res, _ = gpu_mode(m, spec, u0, v0, w0, args.steps, args.warmup, torch, fsei)
         results[m] = res
-        log(f"[bench] mode {m}: {res['ms_per_step']:.3f} ms/step")
+        log(f"[bench] mode {m}: {res['ms_per_step']:.3f} ms/step (median {res['median_step_ms']:.3f})")
     head = modes[0]
     hres = results[head]
+    grid = f"{spec.nx}x{spec.ny}x{spec.nz}"
     line = {
-        "metric": "Poisson-projection solves/s & Gpts/s at 512^2x768; FP32+refine vs FP64, %HBM peak",
+        "metric": f"Poisson-projection solves/s & Gpts/s at {grid}; FP32+refine vs FP64, %HBM peak",
         "value": round(1e3 / hres["ms_per_step"], 3),
         "unit": "solves/s",
         "n_gpus": 1,
@@ -562,35 +645,34 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "fp32_refine" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {spec.nx}x{spec.ny}x{spec.nz} cells, bc x/y "
+        "config": {"workload": f"{args.config}: {grid} cells, bc x/y "
                    f"{'wall' if spec.bcx else 'periodic'}/{'wall' if spec.bcy else 'periodic'}, z walls "
-                   f"tanh {spec.stretch}, u* N(0,1) + Gaussian jet, dt=1; value = {head}",
+                   f"tanh {spec.stretch}, {recipe}, dt=1; value = {head}",
                    "grid": [spec.nx, spec.ny, spec.nz], "mode": head},
-        "roofline": roofline_for(head, hres, ncells),
-        "modes": {m: mode_summary(m, results[m], ncells) for m in modes},
+        "roofline": roofline_for(head, hres, ncells, copy_gbs),
+        "modes": {m: mode_summary(m, results[m], ncells, copy_gbs) for m in modes},
         "gpts_per_s": round(ncells * 1e3 / hres["ms_per_step"] / 1e9, 3),
+        "copy_GBs": round(copy_gbs, 1),
     }
     for m in modes:
-        line["modes"][m]["roofline"] = roofline_for(m, results[m], ncells)
+        line["modes"][m]["roofline"] = roofline_for(m, results[m], ncells, copy_gbs)
     if not args.no_viscous:
         log(f"[bench] viscous step: warmup {args.warmup}, steps {args.steps}")
         vres = gpu_viscous(spec, u0, v0, w0, args.steps, args.warmup, torch, fsei)
         log(f"[bench] viscous step: {vres['ms_per_step']:.3f} ms/step")
-        vs = mode_summary("viscous_fp64", vres, ncells)
-        vs.pop("max_abs_div_after", None)
+        vs = mode_summary("viscous_fp64", vres, ncells, copy_gbs)
         vs["steps_per_s"] = vs.pop("solves_per_s")
         vs["beta"] = vres["beta"]
-        vs["roofline"] = roofline_for("viscous_fp64", vres, ncells)
+        vs["roofline"] = roofline_for("viscous_fp64", vres, ncells, copy_gbs)
         if not args.no_cpu_baseline:
             vs["cpu_baseline"] = cpu_baseline_viscous(spec, vres["beta"])
         line["modes"]["viscous_fp64"] = vs
         log(f"[bench] momentum right-hand side: warmup {args.warmup}, steps {args.steps}")
         mres = gpu_momentum(spec, u0, v0, w0, args.steps, args.warmup, torch, fsei)
         log(f"[bench] momentum right-hand side: {mres['ms_per_step']:.3f} ms/step")
-        ms = mode_summary("momentum_fp64", mres, ncells)
-        ms.pop("max_abs_div_after", None)
+        ms = mode_summary("momentum_fp64", mres, ncells, copy_gbs)
         ms["steps_per_s"] = ms.pop("solves_per_s")
-        ms["roofline"] = roofline_for("momentum_fp64", mres, ncells)
+        ms["roofline"] = roofline_for("momentum_fp64", mres, ncells, copy_gbs)
         if not args.no_cpu_baseline:
             ms["cpu_baseline"] = cpu_baseline_momentum(spec)
         line["modes"]["momentum_fp64"] = ms
@@ -601,10 +683,41 @@ def main():
             ib["cpu_baseline"] = cpu_baseline_ib(spec)
         line["modes"]["ib_mls_fp64"] = ib
         log(f"[bench] IB-MLS: {ib['ms_per_step']:.3f} ms/step")
+    del u0, v0, w0
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle on a bounded sample)")
-        line["cpu_baseline"] = cpu_baseline(spec)
+        log("[bench] cpu baseline (oracle on a bounded sample) and the GPU's error against it")
+        cb, oracle_out = cpu_baseline(spec)
+        line["cpu_baseline"] = cb
+        line["err_vs_oracle"] = err_vs_oracle(spec, oracle_out, torch, fsei)
+        del oracle_out
+    if not args.no_c5:
+        line["c5_solve"] = c5_leg(args, torch, fsei)
     print(json.dumps(line), flush=True)
+
+
+def c5_leg(args, torch, fsei):
+    """Poisson solves on the 768 x 768 x 1024 grid (walls, tanh 3.0, power-law
+    right-hand side): FP32+refine (to rtol 1e-10 or the FP64 rounding floor
+    of this right-hand side) and FP64, each timed over its own steps."""
+    from paper_2103_15187_amd import workloads as W
+    spec = W.CONFIGS["C5"]
+    log(f"[bench] C5 {spec.shape}: power-law right-hand side")
+    f0 = torch.from_numpy(W.rhs_powerlaw(spec, W.SEEDS["C5"])).cuda()
+    copy_gbs = copy_bandwidth(f0, torch)
+    out = {"workload": f"C5: {spec.nx}x{spec.ny}x{spec.nz} cells, walls, z tanh {spec.stretch}, right-hand "
+                       f"side k^-5/3 over 64 modes per axis; one step = one fsei_poisson_solve",
+           "copy_GBs": round(copy_gbs, 1)}
+    for m in ("solve_fp32_refine", "solve_fp64"):
+        log(f"[bench] C5 {m}: warmup 1, steps {args.c5_steps}")
+        res = gpu_solve(m, spec, f0, args.c5_steps, 1, torch, fsei)
+        s = mode_summary(m, res, spec.ncells, copy_gbs)
+        s["roofline"] = roofline_for(m, res, spec.ncells, copy_gbs)
+        out[m] = s
+        log(f"[bench] C5 {m}: {res['ms_per_step']:.3f} ms/step")
+    del f0
+    torch.cuda.empty_cache()
+    return out
 
 
 if __name__ == "__main__":

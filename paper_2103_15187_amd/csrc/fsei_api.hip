@@ -24,7 +24,8 @@ namespace {
 
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
-    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "momentum_rhs", "ib_transfer"};
+    "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "momentum_rhs", "ib_transfer",
+    "xinv_grad"};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
 constexpr int K_RESID_PAIRS = 12;
@@ -35,6 +36,7 @@ constexpr int K_VISC_Y = 16;
 constexpr int K_VISC_Z = 17;
 constexpr int K_MOM_RHS = 18;
 constexpr int K_IB = 19;
+constexpr int K_XINV_GRAD = 20;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -125,30 +127,6 @@ long xblocks(const fsei_plan* p) {
     return ((long)p->ny * p->nz + nl - 1) / nl;
 }
 
-// Row tile of the fused gradient + residual kernel and of the gradient's
-// row order (16 when ny allows, else 8; 8 is forced with FSEI_GR_ROWS=8 for
-// measurement).  The residual-only kernel stays at 8 rows (measured faster
-// there).
-int gr_rows() {
-    static int v = [] {
-        const char* e = getenv("FSEI_GR_ROWS");
-        return e ? atoi(e) : 16;
-    }();
-    return v;
-}
-
-// Gradient kernel selection: 0 = one row per workgroup, one cell pair per
-// lane (nx even, <= 512, ny % 8 == 0); 1 = tiles of 8 rows, cell pairs;
-// 2 = one row per workgroup, one cell per lane.  FSEI_GRAD_CFG overrides the
-// default (0) for measurement; each falls back to 2 where it does not apply.
-int grad_cfg() {
-    static int v = [] {
-        const char* e = getenv("FSEI_GRAD_CFG");
-        return e ? atoi(e) : 0;
-    }();
-    return v;
-}
-
 // pair kernels (gradient, residual norm): lanes own two adjacent x-cells,
 // workgroups kPairRows rows of one plane
 constexpr int kPairRows = 8;
@@ -156,10 +134,10 @@ bool pair_tiles(const fsei_plan* p) { return p->nx % 2 == 0 && p->ny % kPairRows
 bool aligned16(const void* q) { return reinterpret_cast<uintptr_t>(q) % 16 == 0; }
 bool al16(const void* q) { return q == nullptr || aligned16(q); }   // optional pointer
 
-// the fixed-length x kernels (NF = 512) need every tile of rows full and
-// inside one z-plane
+// the fixed-length x kernels (NF = 512 or 768, four sequences = eight rows
+// per tile) need every tile of rows full and inside one z-plane
 bool x_fixed(const fsei_plan* p) {
-    return p->nx == 512 && nseq_x(p) == tile_nseq(2048, 512) && p->ny % (2 * nseq_x(p)) == 0;
+    return (p->nx == 512 || p->nx == 768) && nseq_x(p) == 4 && p->ny % (2 * nseq_x(p)) == 0;
 }
 
 hipStream_t S(const fsei_plan* p) { return (hipStream_t)p->stream; }
@@ -183,19 +161,27 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
     const size_t dyn = 2 * p->nx * sizeof(TO);
     // the fixed path reads and writes every field as aligned column pairs
     const bool al = al16(a.u) && al16(a.v) && al16(a.w) && al16(a.gp) && al16(a.f) && al16(a.src) && al16(a.p) &&
-                    al16(a.out) && al16(a.out_f);
+                    al16(a.p32) && al16(a.out) && al16(a.out_f);
     Timed t(p, slot);
-    if (x_fixed(p) && al)
-        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
+    const dim3 grid((unsigned)xblocks(p));
+    if (x_fixed(p) && al && p->nx == 512)
+        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 512>), grid, dim3(256), dyn, S(p), a);
+    else if (x_fixed(p) && al && p->nx == 768)
+        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 3072, 384, 768>), grid, dim3(384), dyn, S(p), a);
+    else if (x_emax(p->nx) == 3072)
+        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 3072, 384, 0>), grid, dim3(384), dyn, S(p), a);
     else
-        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
+        hipLaunchKernelGGL((k_xfwd<TI, TO, PRO, 2048, 256, 0>), grid, dim3(256), dyn, S(p), a);
 }
 
 template <typename T, typename TP, int EPI>
-void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add32 = nullptr, T* keep = nullptr) {
+void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add32 = nullptr, T* keep = nullptr,
+                 const double* vsum = nullptr) {
     XInvArgs<T, TP> a{};
     a.add32 = add32;
     a.keep = keep;
+    a.vsum = vsum;
+    a.vscale = 1.0 / ((double)p->nx * (double)p->ny * p->lz);
     a.nx = p->nx;
     a.ny = p->ny;
     a.nz = p->nz;
@@ -211,10 +197,69 @@ void launch_xinv(fsei_plan* p, const T* in, TP* out, int slot, const float* add3
     const size_t dyn = 2 * p->nx * sizeof(T);
     const bool al = al16(in) && al16(out) && al16(add32) && al16(keep);
     Timed t(p, slot);
-    if (x_fixed(p) && al)
-        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 512>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
+    const dim3 grid((unsigned)xblocks(p));
+    if (x_fixed(p) && al && p->nx == 512)
+        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 512>), grid, dim3(256), dyn, S(p), a);
+    else if (x_fixed(p) && al && p->nx == 768)
+        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 3072, 384, 768>), grid, dim3(384), dyn, S(p), a);
+    else if (x_emax(p->nx) == 3072)
+        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 3072, 384, 0>), grid, dim3(384), dyn, S(p), a);
     else
-        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 0>), dim3((unsigned)xblocks(p)), dim3(256), dyn, S(p), a);
+        hipLaunchKernelGGL((k_xinv<T, TP, EPI, 2048, 256, 0>), grid, dim3(256), dyn, S(p), a);
+}
+
+// fused x inverse + gradient (FP64): nx of a compiled length, whole 8-row
+// tiles, every field 16-byte aligned
+bool xg_ok(const fsei_plan* p, const void* in, const void* pout, const void* u, const void* v, const void* w) {
+    return (p->nx == 512 || p->nx == 768) && p->ny % kXgRows == 0 && aligned16(in) && al16(pout) &&
+           aligned16(u) && aligned16(v) && aligned16(w);
+}
+
+int xg_planes() {
+    static int v = [] {
+        const char* e = getenv("FSEI_XG_KC");
+        return e ? atoi(e) : 16;
+    }();
+    return v;
+}
+
+void launch_xinv_grad(fsei_plan* p, const double* in, double* pout, double* u, double* v, double* w,
+                      bool adjoint, double dt) {
+    XInvGradArgs a{};
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.bcy = p->bcy;
+    a.kc = xg_planes();
+    a.in = in;
+    a.p = pout;
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    if (!adjoint) {
+        a.cx = -dt / p->dx;
+        a.cy = -dt / p->dy;
+        a.sw = -dt;
+        a.bk = tab<double>(p, T_INV_H);
+        a.gk = tab<double>(p, T_INV_H);
+    } else {
+        a.cx = 1.0 / p->dx;
+        a.cy = 1.0 / p->dy;
+        a.sw = 1.0;
+        a.bk = tab<double>(p, T_INV_DZ);
+        a.gk = tab<double>(p, T_GAM_ADJ);
+    }
+    a.twc = tab<double>(p, T_TWX_C);
+    a.tws = tab<double>(p, T_TWX_S);
+    a.dctc = tab<double>(p, T_DCTX_C);
+    a.dcts = tab<double>(p, T_DCTX_S);
+    const int nchunk = (p->nz + a.kc - 1) / a.kc;
+    const dim3 grid((unsigned)((p->ny / kXgRows) * nchunk));
+    Timed t(p, K_XINV_GRAD);
+    if (p->nx == 768)
+        hipLaunchKernelGGL((k_xinv_grad<768>), grid, dim3(xg_threads<768>()), 2 * 768 * sizeof(double), S(p), a);
+    else
+        hipLaunchKernelGGL((k_xinv_grad<512>), grid, dim3(xg_threads<512>()), 2 * 512 * sizeof(double), S(p), a);
 }
 
 template <typename T, int EMAX, int NTHR>
@@ -256,6 +301,34 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     }
 }
 
+// Compile-time length 768 in y: tiles of 128-byte row segments (8 FP64 /
+// 16 FP32 column pairs) in 768-thread workgroups; needs whole tiles and
+// pair-aligned data.  Returns false where it does not apply.
+template <typename T>
+bool launch_y768(fsei_plan* p, YArgs<T> a, bool inverse) {
+    constexpr int NF = 768, NTHR = 768;
+    constexpr int EMAX = (64 / (int)sizeof(T)) * NF;   // 128-B tile rows
+    constexpr int kPsF = yfwd_pad<T>();
+    static_assert(y_fixed_ok(EMAX, NTHR, NF) && y_fixed_ok(EMAX, NTHR, NF, kPsF) &&
+                      tile_nseq(EMAX, NF, kPsF) == tile_nseq(EMAX, NF) && tile_nseq(EMAX, NF) == EMAX / NF,
+                  "768 y tile");
+    constexpr int NSF = EMAX / NF;
+    if (p->ny != NF || p->nx % (2 * NSF) != 0 || reinterpret_cast<uintptr_t>(a.data) % (2 * sizeof(T)) != 0)
+        return false;
+    a.nseq = NSF;
+    a.ntile = p->nx / (2 * NSF);
+    const unsigned nb = (unsigned)(a.ntile * p->nz);
+    const size_t dyn = 2 * NF * sizeof(T);
+    if (inverse) {
+        Timed t(p, K_YINV);
+        hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, NF>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+    } else {
+        Timed t(p, K_YFWD);
+        hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, NF, kPsF>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+    }
+    return true;
+}
+
 // y tiles: the workgroup's LDS holds enough columns that every row segment
 // it loads or stores covers 128 B (16 doubles / 32 floats) when ny allows
 template <typename T>
@@ -271,6 +344,7 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
     a.tws = tab<T>(p, T_TWY_S);
     a.dctc = tab<T>(p, T_DCTY_C);
     a.dcts = tab<T>(p, T_DCTY_S);
+    if (launch_y768<T>(p, a, inverse)) return;
     // complex elements of a tile whose row segments are 128 B; the tile
     // (2 arrays, padded) plus the 2 ny twiddles must fit in the 160 KB of LDS
     const long want = (long)(64 / sizeof(T)) * p->ny;
@@ -283,22 +357,6 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
         launch_y_cfg<T, 4096, 512>(p, a, inverse);
     else
         launch_y_cfg<T, 8192, 1024>(p, a, inverse);
-}
-
-// Tiling of the z solve: 0 = adjacent modes per lane as one vector: two
-// (FP64, 32 modes per workgroup) or four (FP32, 64 modes per workgroup; two
-// per lane in 1024-thread workgroups when nx % 4 != 0), at most 32 chunks per
-// line (needs nx even); 4 = FP32 with two modes per lane only;
-// 1 = 8 (FP64) / 16 (FP32) modes, one per lane, up to 64 chunks; 2 (FP64) =
-// 16 modes, one per lane, up to 64 chunks in 1024-thread workgroups; 3 = two
-// modes per lane, 16 (FP64) / 32 (FP32) modes, up to 64 chunks.  All tilings do the same work; the
-// environment variable FSEI_Z_CFG selects one for measurement.
-int zcfg() {
-    static int v = [] {
-        const char* e = getenv("FSEI_Z_CFG");
-        return e ? atoi(e) : 0;
-    }();
-    return v;
 }
 
 // chunking of the z lines: P chunks of exactly L rows (L one of the compiled
@@ -316,17 +374,17 @@ bool choose_chunks(int nz, int pmax, int* L, int* P) {
     return false;
 }
 
-template <typename TS, typename TC, int TXL, int NT, bool LIST>
+template <typename TS, typename TC, int TXL, int NT>
 void z_dispatch(fsei_plan* p, ZArgs<TS, TC> a, dim3 grid, int slot) {
     const size_t dyn = 0;
     Timed t(p, slot);
     switch (a.L) {
-        case 4: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 4, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
-        case 8: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 8, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
-        case 12: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 12, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
-        case 16: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 16, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
-        case 24: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 24, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
-        default: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 32, NT, LIST>), grid, dim3(NT), dyn, S(p), a); break;
+        case 4: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 4, NT>), grid, dim3(NT), dyn, S(p), a); break;
+        case 8: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 8, NT>), grid, dim3(NT), dyn, S(p), a); break;
+        case 12: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 12, NT>), grid, dim3(NT), dyn, S(p), a); break;
+        case 16: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 16, NT>), grid, dim3(NT), dyn, S(p), a); break;
+        case 24: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 24, NT>), grid, dim3(NT), dyn, S(p), a); break;
+        default: hipLaunchKernelGGL((k_zsolve<TS, TC, TXL, 32, NT>), grid, dim3(NT), dyn, S(p), a); break;
     }
 }
 
@@ -359,6 +417,9 @@ ZArgs<TS, TC> zargs(const fsei_plan* p, TS* data, int transposed) {
     a.inv_dz = tab<TC>(p, T_INV_DZ);
     a.lamx = tab<TC>(p, T_LAMX);
     a.lamy = tab<TC>(p, T_LAMY);
+    a.lamx64 = tab<double>(p, T_LAMX);
+    a.lamy64 = tab<double>(p, T_LAMY);
+    a.sigma_thr = 0.0;
     return a;
 }
 
@@ -367,92 +428,75 @@ template <typename TS>
 void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
     constexpr bool F32 = std::is_same<TS, float>::value;
     const int nz = p->nz;
+    // Tilings (all do the same arithmetic; chosen by measurement at
+    // 512 x 512 x 768 and 768 x 768 x 1024): adjacent modes per lane as one
+    // vector where nx allows, at most 32 chunks per line; lines longer than
+    // 768 rows (chunks of 32 rows) keep one FP64 mode per lane or take 64
+    // FP32 chunks of at most 16 rows, which avoids register spills.
+    int L = 0, P = 0;
+    const bool c32 = choose_chunks(nz, 32, &L, &P);
     if constexpr (!F32) {
         ZArgs<double, double> a = zargs<double, double>(p, data, transposed);
-        a.sigma_thr = 0.0;
-        int L, P;
-        int cfg = zcfg();
-        // 32 chunks of 32 rows (nz > 768) spill registers with two modes per
-        // lane; one mode per lane (same chunks, same arithmetic) does not
-        if (cfg == 0 && choose_chunks(nz, 32, &L, &P) && L > 24) cfg = 5;
-        if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+        a.sigma_thr = p->sigma_thr;   // the host's threshold, compared in FP64
+        if (c32 && L <= 24 && p->nx % 2 == 0) {
             a.L = L;
             a.P = P;
             zv_dispatch<double, double, 2, 16, 512>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
-        } else if (cfg == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
+        } else if (c32) {
             a.L = L;
             a.P = P;
-            zv_dispatch<double, double, 2, 8, 512>(p, a, dim3((p->nx / 2 + 7) / 8, p->ny));
-
-        } else if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
-            a.L = L;
-            a.P = P;
-            z_dispatch<double, double, 8, 512, false>(p, a, dim3((p->nx + 7) / 8, p->ny), K_ZSOLVE);
-        } else if (cfg == 2 && choose_chunks(nz, 64, &L, &P)) {
-            a.L = L;
-            a.P = P;
-            z_dispatch<double, double, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
-        } else if (choose_chunks(nz, 32, &L, &P)) {
-            a.L = L;
-            a.P = P;
-            z_dispatch<double, double, 16, 512, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
+            z_dispatch<double, double, 16, 512>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
         } else {
             choose_chunks(nz, 64, &L, &P);
             a.L = L;
             a.P = P;
-            z_dispatch<double, double, 8, 512, false>(p, a, dim3((p->nx + 7) / 8, p->ny), K_ZSOLVE);
+            z_dispatch<double, double, 8, 512>(p, a, dim3((p->nx + 7) / 8, p->ny), K_ZSOLVE);
         }
     } else {
         ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
-        a.sigma_thr = (float)p->sigma_thr;
-        int L, P;
-        int cfg = zcfg();
-        // 32 chunks of 32 rows (nz > 768) spill registers in the default
-        // tiling; 64 chunks of at most 16 rows with two modes per lane do
-        // not.  (In FP64 the 64-chunk tiling left an 8x larger residual at
-        // 768 x 768 x 1024, 6.2e-9 -> 4.9e-8, so FP64 keeps 32 chunks.)
-        if (cfg == 0 && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P) && L > 24) cfg = 3;
-        if (cfg == 0 && p->nx % 4 == 0 && choose_chunks(nz, 32, &L, &P)) {
+        a.sigma_thr = p->sigma_thr;   // the host's threshold, compared in FP64
+        if (c32 && L <= 24 && p->nx % 4 == 0) {
             a.L = L;
             a.P = P;
             zv_dispatch<float, float, 4, 16, 512>(p, a, dim3((p->nx / 4 + 15) / 16, p->ny));
-        } else if ((cfg == 0 || cfg == 4) && p->nx % 2 == 0 && choose_chunks(nz, 32, &L, &P)) {
+        } else if (c32 && L <= 24 && p->nx % 2 == 0) {
             a.L = L;
             a.P = P;
             zv_dispatch<float, float, 2, 32, 1024>(p, a, dim3((p->nx / 2 + 31) / 32, p->ny));
-        } else if (cfg == 3 && p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
+        } else if (p->nx % 2 == 0 && choose_chunks(nz, 64, &L, &P)) {
             a.L = L;
             a.P = P;
             zv_dispatch<float, float, 2, 16, 1024>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
-        } else if (cfg == 1 && choose_chunks(nz, 64, &L, &P)) {
+        } else if (c32) {
             a.L = L;
             a.P = P;
-            z_dispatch<float, float, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
-        } else if (choose_chunks(nz, 32, &L, &P)) {
-            a.L = L;
-            a.P = P;
-            z_dispatch<float, float, 32, 1024, false>(p, a, dim3((p->nx + 31) / 32, p->ny), K_ZSOLVE);
+            z_dispatch<float, float, 32, 1024>(p, a, dim3((p->nx + 31) / 32, p->ny), K_ZSOLVE);
         } else {
             choose_chunks(nz, 64, &L, &P);
             a.L = L;
             a.P = P;
-            z_dispatch<float, float, 16, 1024, false>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
+            z_dispatch<float, float, 16, 1024>(p, a, dim3((p->nx + 15) / 16, p->ny), K_ZSOLVE);
         }
-        if (p->nlist > 0) {
-            ZArgs<float, double> b = zargs<float, double>(p, data, transposed);
-            b.list = zlist(p);
-            b.nlist = p->nlist;
-            if (choose_chunks(nz, 32, &L, &P)) {
-                b.L = L;
-                b.P = P;
-                z_dispatch<float, double, 16, 512, true>(p, b, dim3((p->nlist + 15) / 16), K_ZLIST);
-            } else {
-                choose_chunks(nz, 64, &L, &P);
-                b.L = L;
-                b.P = P;
-                z_dispatch<float, double, 8, 512, true>(p, b, dim3((p->nlist + 7) / 8), K_ZLIST);
-            }
-        }
+    }
+    if (p->nlist > 0) {
+        ZSeqArgs<TS> b{};
+        b.nx = p->nx;
+        b.nz = nz;
+        b.nlist = p->nlist;
+        b.transposed = transposed;
+        b.stride = (size_t)p->nx * p->ny;
+        b.data = data;
+        b.list = zlist(p);
+        b.ys = reinterpret_cast<double*>((char*)p->ws + p->ws_seq);
+        b.cps = b.ys + (size_t)p->nlist * nz;
+        b.za = tab<double>(p, T_ZA);
+        b.zc = tab<double>(p, T_ZC);
+        b.lamx = tab<double>(p, T_LAMX);
+        b.lamy = tab<double>(p, T_LAMY);
+        b.dz = tab<double>(p, T_DZ);
+        b.scale = 1.0 / ((double)p->nx * (double)p->ny);
+        Timed t(p, K_ZLIST);
+        hipLaunchKernelGGL((k_zline_seq<TS>), dim3((unsigned)((p->nlist + 63) / 64)), dim3(64), 0, S(p), b);
     }
     ZeroArgs<TS> z{};
     z.nz = nz;
@@ -467,6 +511,22 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
     z.scal = record_mean ? scalars(p) : nullptr;
     Timed t(p, K_PREP);
     hipLaunchKernelGGL((k_zero_mode<TS>), dim3(1), dim3(256), 0, S(p), z);
+}
+
+// k_grad_row2 with the smallest workgroup that gives every cell pair of a
+// row a lane (np = nx / 2 <= 512 pairs)
+template <typename TIO, typename TP, int GJ>
+void launch_grad_row2(fsei_plan* p, const GradArgs<TIO, TP>& a, dim3 grid, int np) {
+    if (np > 384)
+        hipLaunchKernelGGL((k_grad_row2<TIO, TP, 512, GJ>), grid, dim3(512), 0, S(p), a);
+    else if (np > 256)
+        hipLaunchKernelGGL((k_grad_row2<TIO, TP, 384, GJ>), grid, dim3(384), 0, S(p), a);
+    else if (np > 128)
+        hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256, GJ>), grid, dim3(256), 0, S(p), a);
+    else if (np > 64)
+        hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128, GJ>), grid, dim3(128), 0, S(p), a);
+    else
+        hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64, GJ>), grid, dim3(64), 0, S(p), a);
 }
 
 template <typename TIO, typename TP>
@@ -496,35 +556,15 @@ void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoin
     }
     Timed t(p, K_GRAD);
     const bool al = aligned16(u) && aligned16(v) && aligned16(w) && aligned16(pr);
-    if (grad_cfg() == 0 && p->nx % 2 == 0 && p->nx <= 512 && p->ny % 8 == 0 && al) {
+    const int np = p->nx / 2;
+    if (p->nx % 2 == 0 && np <= 512 && p->ny % 8 == 0 && al) {
+        // one row per workgroup, one cell pair per lane; rows in 16-row
+        // tiles when ny allows (fewer re-read halo rows), else 8
         const dim3 grid((unsigned)((long)p->ny * p->nz));
-        const int np = p->nx / 2;
-        if (p->ny % 16 == 0 && gr_rows() == 16) {
-            if (np > 128)
-                hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256, 16>), grid, dim3(256), 0, S(p), a);
-            else if (np > 64)
-                hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128, 16>), grid, dim3(128), 0, S(p), a);
-            else
-                hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64, 16>), grid, dim3(64), 0, S(p), a);
-            return;
-        }
-        if (np > 128)
-            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 256, 8>), grid, dim3(256), 0, S(p), a);
-        else if (np > 64)
-            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 128, 8>), grid, dim3(128), 0, S(p), a);
+        if (p->ny % 16 == 0)
+            launch_grad_row2<TIO, TP, 16>(p, a, grid, np);
         else
-            hipLaunchKernelGGL((k_grad_row2<TIO, TP, 64, 8>), grid, dim3(64), 0, S(p), a);
-        return;
-    }
-    if (grad_cfg() == 1 && pair_tiles(p) && al) {
-        const dim3 grid((unsigned)((long)(p->ny / kPairRows) * p->nz));
-        const int np = p->nx / 2;
-        if (np >= 256)
-            hipLaunchKernelGGL((k_grad_pairs<TIO, TP, 256, kPairRows>), grid, dim3(256), 0, S(p), a);
-        else if (np > 64)
-            hipLaunchKernelGGL((k_grad_pairs<TIO, TP, 128, kPairRows>), grid, dim3(128), 0, S(p), a);
-        else
-            hipLaunchKernelGGL((k_grad_pairs<TIO, TP, 64, kPairRows>), grid, dim3(64), 0, S(p), a);
+            launch_grad_row2<TIO, TP, 8>(p, a, grid, np);
         return;
     }
     hipLaunchKernelGGL((k_grad<TIO, TP>), dim3((unsigned)((long)p->ny * p->nz)), dim3(256), 0, S(p), a);
@@ -547,6 +587,7 @@ long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr, float* out
     a.za = tab<double>(p, T_ZA);
     a.zc = tab<double>(p, T_ZC);
     a.scal = scalars(p);
+    a.dz = tab<double>(p, T_DZ);
     a.partials = partials(p);
     a.out = out32;
     const long nb = (long)(p->ny / kPairRows) * p->nz;
@@ -554,14 +595,18 @@ long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr, float* out
     const int np = p->nx / 2;
     Timed t(p, out32 ? K_RESID_PAIRS : K_RESNORM);
     if (out32) {
-        if (np >= 256)
+        if (np == 384)
+            hipLaunchKernelGGL((k_resid_pairs<384, kPairRows, true, TPP>), grid, dim3(384), 0, S(p), a);
+        else if (np >= 256)
             hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, true, TPP>), grid, dim3(256), 0, S(p), a);
         else if (np > 64)
             hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, true, TPP>), grid, dim3(128), 0, S(p), a);
         else
             hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, true, TPP>), grid, dim3(64), 0, S(p), a);
     } else {
-        if (np >= 256)
+        if (np == 384)
+            hipLaunchKernelGGL((k_resid_pairs<384, kPairRows, false, TPP>), grid, dim3(384), 0, S(p), a);
+        else if (np >= 256)
             hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, false, TPP>), grid, dim3(256), 0, S(p), a);
         else if (np > 64)
             hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, false, TPP>), grid, dim3(128), 0, S(p), a);
@@ -602,13 +647,15 @@ long launch_grad_resid(fsei_plan* p, double* u, double* v, double* w, const doub
     a.partials = partials(p);
     // 16-row tiles halve the re-read halo rows (j-1 of the first row, j+1 of
     // the last) against 8-row tiles when ny allows
-    const int rows = (gr_rows() == 16 && p->ny % 16 == 0) ? 16 : kPairRows;
+    const int rows = (p->ny % 16 == 0) ? 16 : kPairRows;
     const long nb = (long)(p->ny / rows) * p->nz;
     const dim3 grid((unsigned)nb);
     const int np = p->nx / 2;
     Timed t(p, K_GRAD_RESID);
     if (rows == 16) {
-        if (np >= 256)
+        if (np == 384)
+            hipLaunchKernelGGL((k_grad_resid<384, 16, DELTA>), grid, dim3(384), 0, S(p), a);
+        else if (np >= 256)
             hipLaunchKernelGGL((k_grad_resid<256, 16, DELTA>), grid, dim3(256), 0, S(p), a);
         else if (np > 64)
             hipLaunchKernelGGL((k_grad_resid<128, 16, DELTA>), grid, dim3(128), 0, S(p), a);
@@ -616,7 +663,9 @@ long launch_grad_resid(fsei_plan* p, double* u, double* v, double* w, const doub
             hipLaunchKernelGGL((k_grad_resid<64, 16, DELTA>), grid, dim3(64), 0, S(p), a);
         return nb;
     }
-    if (np >= 256)
+    if (np == 384)
+        hipLaunchKernelGGL((k_grad_resid<384, kPairRows, DELTA>), grid, dim3(384), 0, S(p), a);
+    else if (np >= 256)
         hipLaunchKernelGGL((k_grad_resid<256, kPairRows, DELTA>), grid, dim3(256), 0, S(p), a);
     else if (np > 64)
         hipLaunchKernelGGL((k_grad_resid<128, kPairRows, DELTA>), grid, dim3(128), 0, S(p), a);
@@ -809,6 +858,7 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     r.zc = tab<double>(p, T_ZC);
     r.scal = scalars(p);
     r.partials = partials(p);
+    r.dzw = tab<double>(p, T_DZ);   // third partial: sum dz_k p of the iterate
     int it = 0;
     double rel = -1.0, rel_prev = -1.0;
     bool converged = false;
@@ -822,7 +872,7 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
     bool first_pending = false;
     double vmean = 0.0;
     auto residual_norm = [&]() -> fsei_status {
-        reduce_partials(p, 1, false, nres);   // scalars[1..3]: sum r^2, sum r, 0
+        reduce_partials(p, 1, false, nres);   // scalars[1..3]: sum r^2, sum r, (sum dz_k p or 0)
         double h[11];
         fsei_status st = read_scalars(p, h, first_pending ? 11 : 8);
         if (st != FSEI_OK) return st;
@@ -858,8 +908,20 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
             launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
         }
     };
+    static const bool fused_resid = getenv("FSEI_RESID_FUSED") != nullptr;
     auto resid_pass = [&]() {
-        if (pairs) {
+        if (fused_resid && p_in_32) {
+            XFwdArgs<double, float> r32 = r;
+            r32.p = nullptr;
+            r32.p32 = p32;
+            r32.out = w32;
+            nres = -1;
+            launch_xfwd<double, float, PRO_RESID_F>(p, r32, K_RESID_XFWD);
+        } else if (fused_resid) {
+            r.out = w32;
+            nres = -1;
+            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
+        } else if (pairs) {
             nres = p_in_32 ? launch_resid_pairs(p, f64, (const float*)p32, w32)
                            : launch_resid_pairs(p, f64, (const double*)p64, w32);
             XFwdArgs<float, float> t{};
@@ -873,29 +935,34 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         }
     };
     resid_pass();
-    if (p->rtol > 0.0) {
-        if (p->max_iter > 0) {
-            reduce_partials(p, 8, false, nres);
-            first_pending = true;
-        } else {
-            fsei_status st = residual_norm();
-            if (st != FSEI_OK) return st;
-        }
+    if (p->max_iter > 0) {
+        // scalars[8..10]: the first solve's sum r^2, sum r and sum dz_k p.
+        // The last is its V-integral: the first correction subtracts the
+        // V-mean it gives, so p is pinned in FP64 (later corrections are
+        // solves of residuals, whose V-mean is zero).
+        reduce_partials(p, 8, false, nres);
+        first_pending = p->rtol > 0.0;
+    } else if (p->rtol > 0.0) {
+        fsei_status st = residual_norm();
+        if (st != FSEI_OK) return st;
     }
+    const double* vsum0 = scalars(p) + 10;
     const bool fuse = g != nullptr && pairs && p->rtol > 0.0 && aligned16(g->u) && aligned16(g->v) &&
                       aligned16(g->w);
     while (!converged && it < p->max_iter) {
         launch_y<float>(p, w32, false);
         launch_z<float>(p, w32, 0, false);
         launch_y<float>(p, w32, true);
+        const double* vsum = (it == 0) ? vsum0 : nullptr;
         if (p_in_32) {
-            launch_xinv<float, double, EPI_ADDF>(p, w32, p64, K_XINV_ACC, p32);   // p64 = p32 + delta
+            // p64 = (p32 - its V-mean) + delta
+            launch_xinv<float, double, EPI_ADDF>(p, w32, p64, K_XINV_ACC, p32, nullptr, vsum);
             p_in_32 = false;
         } else if (fuse && g->applied) {
             // p64 += delta, and delta itself kept (in w32) for its gradient
-            launch_xinv<float, double, EPI_ACC_KEEP>(p, w32, p64, K_XINV_ACC, nullptr, w32);
+            launch_xinv<float, double, EPI_ACC_KEEP>(p, w32, p64, K_XINV_ACC, nullptr, w32, vsum);
         } else {
-            launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC);
+            launch_xinv<float, double, EPI_ACC>(p, w32, p64, K_XINV_ACC, nullptr, nullptr, vsum);
         }
         ++it;
         measured = false;
@@ -1025,12 +1092,13 @@ fsei_status fsei_poisson_solve(fsei_plan* p, const double* f, double* out, fsei_
     return FSEI_OK;
 }
 
-fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* pout, double dt, fsei_info* info) {
-    fsei_status st = ready(p);
-    if (st != FSEI_OK) return st;
-    if (!u || !v || !w) return FSEI_ERR_ARG;
-    if (!good_dt(dt)) return FSEI_ERR_ARG;
-    if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+}  // extern "C"
+
+namespace {
+
+// the projection on the plan's current workspace (arguments checked by the caller)
+fsei_status project_impl(fsei_plan* p, double* u, double* v, double* w, double* pout, double dt, fsei_info* info) {
+    fsei_status st = FSEI_OK;
     if (p->precision == FSEI_PREC_FP32_REFINE) {
         double* p64 = pout ? pout : static_cast<double*>(field3(p));
         XFwdArgs<double, float> a = div_args<double, float>(p, u, v, w, nullptr, false, dt);
@@ -1041,15 +1109,24 @@ fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* 
         fsei_status st2 = check_hip();
         return (st2 != FSEI_OK) ? st2 : st;
     }
-    double* buf = pout ? pout : static_cast<double*>(field1(p));
+    // the transform chain runs in the workspace field when the x inverse is
+    // fused with the gradient (its halo rows must not be overwritten by a
+    // neighbouring tile's p), else in the caller's p when given
+    double* ws1 = static_cast<double*>(field1(p));
+    const bool fused = xg_ok(p, ws1, pout, u, v, w);
+    double* buf = (pout && !fused) ? pout : ws1;
     XFwdArgs<double, double> a = div_args<double, double>(p, u, v, w, nullptr, false, dt);
     a.out = buf;
     launch_xfwd<double, double, PRO_DIV>(p, a, K_XFWD);
     launch_y<double>(p, buf, false);
     launch_z<double>(p, buf, 0, true);
     launch_y<double>(p, buf, true);
-    launch_xinv<double, double, EPI_STORE>(p, buf, buf, K_XINV);
-    launch_grad<double, double>(p, u, v, w, buf, false, dt);
+    if (fused) {
+        launch_xinv_grad(p, buf, pout, u, v, w, false, dt);
+    } else {
+        launch_xinv<double, double, EPI_STORE>(p, buf, buf, K_XINV);
+        launch_grad<double, double>(p, u, v, w, buf, false, dt);
+    }
     st = check_hip();
     if (st != FSEI_OK) return st;
     if (info) {
@@ -1062,6 +1139,19 @@ fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* 
         info->floor_reached = 0;
     }
     return FSEI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* pout, double dt, fsei_info* info) {
+    fsei_status st = ready(p);
+    if (st != FSEI_OK) return st;
+    if (!u || !v || !w) return FSEI_ERR_ARG;
+    if (!good_dt(dt)) return FSEI_ERR_ARG;
+    if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    return project_impl(p, u, v, w, pout, dt, info);
 }
 
 fsei_status fsei_project_backward(fsei_plan* p, double* gu, double* gv, double* gw, const double* gp, double dt) {
@@ -1077,8 +1167,12 @@ fsei_status fsei_project_backward(fsei_plan* p, double* gu, double* gv, double* 
     launch_y<double>(p, buf, false);
     launch_z<double>(p, buf, 1, false);
     launch_y<double>(p, buf, true);
-    launch_xinv<double, double, EPI_STORE>(p, buf, buf, K_XINV);
-    launch_grad<double, double>(p, gu, gv, gw, buf, true, dt);
+    if (xg_ok(p, buf, nullptr, gu, gv, gw)) {
+        launch_xinv_grad(p, buf, nullptr, gu, gv, gw, true, dt);
+    } else {
+        launch_xinv<double, double, EPI_STORE>(p, buf, buf, K_XINV);
+        launch_grad<double, double>(p, gu, gv, gw, buf, true, dt);
+    }
     return check_hip();
 }
 

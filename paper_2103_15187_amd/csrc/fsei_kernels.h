@@ -55,11 +55,15 @@ __device__ __forceinline__ float zrcp(float x) {
 
 template <typename TS, typename TC>
 struct ZArgs {
-    int nx, ny, nz, L, P, transposed, nlist;
+    int nx, ny, nz, L, P, transposed;
     TS* data;
-    const int* list;      // LIST mode: mode indices qy*nx + qx
     TC scale;             // 1/(nx ny)
-    TC sigma_thr;         // dense mode: skip lines with |sigma| < sigma_thr
+    // skip the lines with |lamx64 + lamy64| < sigma_thr, tested in FP64 on
+    // the FP64 tables with the host's own expression, so that a line is
+    // solved here exactly when the host left it out of its near-singular list
+    double sigma_thr;
+    const double* lamx64;
+    const double* lamy64;
     const TC* za;
     const TC* zc;
     const TC* zb0;
@@ -69,7 +73,7 @@ struct ZArgs {
     const TC* lamy;
 };
 
-template <typename TS, typename TC, int TXL, int L, int NT, bool LIST>
+template <typename TS, typename TC, int TXL, int L, int NT>
 __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
     constexpr int PMAX = NT / TXL;
     __shared__ TC sh[4][NT];
@@ -94,26 +98,14 @@ __global__ __launch_bounds__(NT) void k_zsolve(ZArgs<TS, TC> a) {
     const int ln = threadIdx.x % TXL;
     const int p = threadIdx.x / TXL;
     const size_t stride = (size_t)nx * a.ny;
-    int qx, qy;
-    bool active;
-    if constexpr (LIST) {
-        const int li = blockIdx.x * TXL + ln;
-        active = li < a.nlist;
-        const int line = active ? a.list[li] : 0;
-        qy = line / nx;
-        qx = line - qy * nx;
-    } else {
-        qx = blockIdx.x * TXL + ln;
-        qy = blockIdx.y;
-        active = qx < nx;
-    }
+    const int qx = blockIdx.x * TXL + ln;
+    const int qy = blockIdx.y;
+    bool active = qx < nx;
     TC sigma = (TC)-1;
     if (active) {
         sigma = a.lamx[qx] + a.lamy[qy];
         if (qx == 0 && qy == 0) active = false;
-        if constexpr (!LIST) {
-            if (fabs(sigma) < a.sigma_thr) active = false;
-        }
+        if (fabs(a.lamx64[qx] + a.lamy64[qy]) < a.sigma_thr) active = false;
         if (!active) sigma = (TC)-1;
     }
     const bool inrange = p < P;
@@ -285,7 +277,7 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
         sigma[h] = (TC)-1;
         if (act[h]) {
             sigma[h] = a.lamx[qx] + a.lamy[qy];
-            if ((qx == 0 && qy == 0) || fabs(sigma[h]) < a.sigma_thr) act[h] = false;
+            if ((qx == 0 && qy == 0) || fabs(a.lamx64[qx] + a.lamy64[qy]) < a.sigma_thr) act[h] = false;
             if (!act[h]) sigma[h] = (TC)-1;
         }
         anyl = anyl || act[h];
@@ -456,6 +448,110 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
                         if (act[h]) outs[(size_t)t * M * strideV + h] = (TS)(F[h][t] * so);
                 }
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Near-singular mode lines: |lambda_x + lambda_y| below the plan's threshold
+// (condition 1 + 4 / (dz_min^2 |sigma|) above 1e4).  One lane per line,
+// sequential Thomas in FP64 with the pivots in row-sum form.  With zero-flux
+// walls every row of L_z + sigma sums to sigma, so the pivot
+//     d_k = b_k - a_k c_{k-1} / d_{k-1},   b_k = -(a_k + c_k) + sigma,
+// equals g_k - c_k with g_k = sigma - a_k g_{k-1} / d_{k-1}, g_0 = sigma: every
+// term has the sign of sigma, nothing cancels.  Forming b_k first rounds the
+// small sigma against a_k + c_k, which costs up to ~1e-11 relative error at
+// condition 1e8 in FP64 (768 x 768 x 1024, tanh 3.0); this form stays at
+// ~1e-15.  The eliminated right-hand side and the ratios c_k / d_k go to an
+// FP64 scratch (line-contiguous across lanes: coalesced), the back
+// substitution writes the field.
+// ---------------------------------------------------------------------------
+template <typename TS>
+struct ZSeqArgs {
+    int nx, nz, nlist, transposed;
+    size_t stride;          // nx * ny
+    TS* data;
+    const int* list;        // line indices qy * nx + qx, ascending
+    double* ys;             // scratch, nlist * nz: eliminated right-hand side
+    double* cps;            // scratch, nlist * nz: c_k / d_k
+    const double* za;
+    const double* zc;
+    const double* lamx;
+    const double* lamy;
+    const double* dz;       // transposed solve: input scaled by 1/dz_k, output by dz_k
+    double scale;           // 1 / (nx ny)
+};
+
+template <typename TS>
+__global__ __launch_bounds__(64) void k_zline_seq(ZSeqArgs<TS> a) {
+    // Rows go in batches of B; the next batch's loads are issued before the
+    // current batch is eliminated, so memory latency overlaps the sweep.
+    constexpr int B = 32;
+    const int li = blockIdx.x * 64 + threadIdx.x;
+    if (li >= a.nlist) return;
+    const int line = a.list[li];
+    const int qy = line / a.nx, qx = line - qy * a.nx;
+    const double sigma = a.lamx[qx] + a.lamy[qy];
+    const TS* __restrict__ colr = a.data + line;
+    const int nz = a.nz, nl = a.nlist;
+    const size_t st = a.stride;
+    double* __restrict__ ys = a.ys + li;
+    double* __restrict__ cps = a.cps + li;
+    auto load_rows = [&](int k0, double* f) {
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const int k = k0 + t;
+            f[t] = (k < nz) ? (double)colr[(size_t)k * st] : 0.0;
+        }
+    };
+    double q = 1.0, y = 0.0;   // q = g_{k-1} / d_{k-1} (1 before the first row)
+    double fa[B], fb[B];
+    load_rows(0, fa);
+    for (int k0 = 0; k0 < nz; k0 += B) {
+        if (k0 + B < nz) load_rows(k0 + B, fb);
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const int k = k0 + t;
+            if (k < nz) {
+                const double A = (k > 0) ? a.za[k] : 0.0, C = (k + 1 < nz) ? a.zc[k] : 0.0;
+                const double fs = fa[t] * (a.transposed ? a.scale / a.dz[k] : a.scale);
+                const double g = sigma - A * q;
+                const double d = g - C;
+                q = g / d;
+                y = (fs - A * y) / d;
+                ys[(size_t)k * nl] = y;
+                cps[(size_t)k * nl] = C / d;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < B; ++t) fa[t] = fb[t];
+    }
+    TS* __restrict__ colw = a.data + line;
+    auto load_back = [&](int k1, double* yv, double* cv) {
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const int k = k1 - t;
+            yv[t] = (k >= 0) ? ys[(size_t)k * nl] : 0.0;
+            cv[t] = (k >= 0) ? cps[(size_t)k * nl] : 0.0;
+        }
+    };
+    double x = 0.0;
+    double ya[B], ca[B], yb[B], cb[B];
+    load_back(nz - 1, ya, ca);
+    for (int k1 = nz - 1; k1 >= 0; k1 -= B) {
+        if (k1 - B >= 0) load_back(k1 - B, yb, cb);
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            const int k = k1 - t;
+            if (k >= 0) {
+                x = ya[t] - ca[t] * x;
+                colw[(size_t)k * st] = (TS)(a.transposed ? x * a.dz[k] : x);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < B; ++t) {
+            ya[t] = yb[t];
+            ca[t] = cb[t];
         }
     }
 }
@@ -637,74 +733,6 @@ __global__ __launch_bounds__(256) void k_grad(GradArgs<TIO, TP> a) {
     }
 }
 
-// Pair kernels: the same gradient correction with every lane owning two
-// adjacent x-cells (one 16-byte FP64 / 8-byte FP32 access per field), on
-// tiles of RJ rows of one z-plane.  Tiles go (row tile, plane) with the plane
-// fastest, so the k-1 rows of p were read by the previous workgroup on the
-// same XCD; the j-1 row comes from the lane's previous row in registers.
-// Launched when nx is even, ny % RJ == 0 and all fields are 16-byte aligned.
-template <typename TIO, typename TP, int NT, int RJ>
-__global__ __launch_bounds__(NT) void k_grad_pairs(GradArgs<TIO, TP> a) {
-    using V = typename Vec2T<TIO>::type;
-    using VP = typename Vec2T<TP>::type;
-    constexpr int RB = 4;   // rows per batch: all loads of a batch are issued before the first store
-    static_assert(RJ % RB == 0, "whole batches");
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
-    const int jt = b / nz;
-    const int k = b - jt * nz;
-    const int j0 = jt * RJ;
-    const size_t nxy = (size_t)nx * ny;
-    const TP* __restrict__ pk = a.p + (size_t)k * nxy;
-    const TP* __restrict__ pkm = (k > 0) ? pk - nxy : pk;   // unused at k = 0
-    TIO* __restrict__ u = a.u + (size_t)k * nxy;
-    TIO* __restrict__ v = a.v + (size_t)k * nxy;
-    TIO* __restrict__ w = a.w + (size_t)k * nxy;
-    const TIO bk = a.bk[k], gk = a.gk[k];
-    const bool wallx = a.bcx == FSEI_BC_WALL, wally = a.bcy == FSEI_BC_WALL;
-    // row j0 - 1 (periodic wrap; at a wall the v faces of row 0 are written 0)
-    const int jprev = (j0 > 0) ? j0 - 1 : ny - 1;
-    for (int c = threadIdx.x; 2 * c < nx; c += NT) {
-        const unsigned i = 2u * (unsigned)c;
-        const unsigned im = (i > 0) ? i - 1 : (unsigned)nx - 1;
-        VP prev = *reinterpret_cast<const VP*>(pk + (size_t)jprev * nx + i);
-#pragma unroll
-        for (int l0 = 0; l0 < RJ; l0 += RB) {
-            VP pc[RB], pz[RB];
-            TP pxm[RB];
-            V uo[RB], vo[RB], wo[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const size_t ro = (size_t)(j0 + l0 + r) * nx;
-                pc[r] = *reinterpret_cast<const VP*>(pk + ro + i);
-                pxm[r] = pk[ro + im];
-                pz[r] = *reinterpret_cast<const VP*>(pkm + ro + i);
-                uo[r] = *reinterpret_cast<const V*>(u + ro + i);
-                vo[r] = *reinterpret_cast<const V*>(v + ro + i);
-                wo[r] = *reinterpret_cast<const V*>(w + ro + i);
-            }
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                const int j = j0 + l0 + r;
-                const size_t ro = (size_t)j * nx;
-                const VP pp = (r == 0) ? prev : pc[r > 0 ? r - 1 : 0];
-                V un, vn, wn;
-                un.x = (wallx && i == 0) ? (TIO)0 : uo[r].x + a.cx * ((TIO)pc[r].x - (TIO)pxm[r]);
-                un.y = uo[r].y + a.cx * ((TIO)pc[r].y - (TIO)pc[r].x);
-                const bool v0 = wally && j == 0;
-                vn.x = v0 ? (TIO)0 : vo[r].x + a.cy * ((TIO)pc[r].x - (TIO)pp.x);
-                vn.y = v0 ? (TIO)0 : vo[r].y + a.cy * ((TIO)pc[r].y - (TIO)pp.y);
-                wn.x = (k == 0) ? (TIO)0 : wo[r].x + a.sw * (bk * (TIO)pc[r].x - gk * (TIO)pz[r].x);
-                wn.y = (k == 0) ? (TIO)0 : wo[r].y + a.sw * (bk * (TIO)pc[r].y - gk * (TIO)pz[r].y);
-                *reinterpret_cast<V*>(u + ro + i) = un;
-                *reinterpret_cast<V*>(v + ro + i) = vn;
-                *reinterpret_cast<V*>(w + ro + i) = wn;
-            }
-            prev = pc[RB - 1];
-        }
-    }
-}
-
 // One x-row per workgroup, one cell pair per lane (NT >= nx / 2): the
 // simplest streaming shape, which runs closest to the HBM ceiling.  Rows in
 // tiles of GJ rows (ny % GJ == 0), plane by plane inside a tile (as k_grad).
@@ -753,9 +781,13 @@ __global__ __launch_bounds__(NT) void k_grad_row2(GradArgs<TIO, TP> a) {
 
 // ---------------------------------------------------------------------------
 // FP64 residual of the refinement, r = (f - mean) - L p: per-block
-// (sum r^2, sum r, 0) partials and, with WRITE, r rounded to FP32 for the
-// next correction solve.  Same pair tiling as k_grad_pairs; the j-1 / j+1
-// rows of p rotate through registers.
+// (sum r^2, sum r, sum dz_k p) partials and, with WRITE, r rounded to FP32
+// for the next correction solve.  The third sum is the volume integral of the
+// iterate (over dx dy): the residual is blind to constants, so this is what
+// lets the next correction pin the V-mean of p in FP64.  Lanes own two
+// adjacent x-cells (16-byte accesses), workgroups RJ rows of one z-plane,
+// tiles plane-fastest (the k-1 rows of p were read by the previous
+// workgroup on the same XCD); the j-1 / j+1 rows rotate through registers.
 // ---------------------------------------------------------------------------
 template <typename TPP>
 struct ResArgs {
@@ -766,6 +798,7 @@ struct ResArgs {
     const double* za;
     const double* zc;
     const double* scal;   // scal[0] = removed mean
+    const double* dz;     // cell widths dz_k (third partial)
     double* partials;
     float* out;           // WRITE: the residual in FP32 (input of the next correction)
 };
@@ -795,7 +828,7 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
     const bool hzm = k > 0, hzp = k + 1 < nz;
     const bool pery = a.bcy == FSEI_BC_PERIODIC, perx = a.bcx == FSEI_BC_PERIODIC;
     const double mean = a.scal[0];
-    double ss = 0.0, s1 = 0.0;
+    double ss = 0.0, s1 = 0.0, sp = 0.0;
     for (int c = threadIdx.x; 2 * c < nx; c += NT) {
         const unsigned i = 2u * (unsigned)c;
         // x neighbours of the pair: i - 1 and i + 2 (wrapped)
@@ -836,6 +869,7 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
                 const double r1 = (fc[r].y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1);
                 ss += r0 * r0 + r1 * r1;
                 s1 += r0 + r1;
+                sp += pc.x + pc.y;
                 if constexpr (WRITE)
                     *reinterpret_cast<float2*>(a.out + (size_t)k * nxy + (size_t)j * nx + i) =
                         make_float2((float)r0, (float)r1);
@@ -844,12 +878,12 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
             }
         }
     }
-    double s2 = 0.0;
+    double s2 = a.dz[k] * sp;   // every row of the block is in plane k
     block_sum3<NT>(ss, s1, s2, sred);
     if (threadIdx.x == 0) {
         a.partials[3 * blockIdx.x] = ss;
         a.partials[3 * blockIdx.x + 1] = s1;
-        a.partials[3 * blockIdx.x + 2] = 0.0;
+        a.partials[3 * blockIdx.x + 2] = s2;
     }
 }
 

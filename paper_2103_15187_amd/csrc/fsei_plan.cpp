@@ -41,12 +41,12 @@ static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 void compute_layout(fsei_plan_impl* p) {
     const size_t N = p->ncells();
-    // FP32 plans route the near-singular lowest-mode lines to FP64:
-    // kappa = 1 + 4 / (dz_min^2 |sigma|) > kappa_star
+    // The near-singular lowest-mode lines, kappa = 1 + 4 / (dz_min^2 |sigma|)
+    // > kappa_star, are solved one per lane in FP64 with row-sum pivots (in
+    // every precision mode); the tiled solvers skip them.
     p->list_host.clear();
-    p->sigma_thr = 0.0;
-    if (p->precision != FSEI_PREC_FP64) {
-        p->sigma_thr = 4.0 / (p->dzmin * p->dzmin * (p->kappa_star - 1.0));
+    p->sigma_thr = 4.0 / (p->dzmin * p->dzmin * (p->kappa_star - 1.0));
+    {
         const double* lx = p->tab_d.data() + p->tab_off[T_LAMX];
         const double* ly = p->tab_d.data() + p->tab_off[T_LAMY];
         for (int qy = 0; qy < p->ny; ++qy)
@@ -74,6 +74,10 @@ void compute_layout(fsei_plan_impl* p) {
     p->ws_list = off;
     p->ws_list_bytes = (size_t)p->nlist * sizeof(int);
     off = round_up(off + p->ws_list_bytes, kAlign);
+    // FP64 scratch of the near-singular lines: eliminated right-hand side and
+    // c_k / d_k, nlist * nz each
+    p->ws_seq = off;
+    off = round_up(off + 2 * (size_t)p->nlist * (size_t)p->nz * sizeof(double), kAlign);
     // viscous line-solve tables (3 components x 3 directions)
     p->visc_L[0] = visc_chunk(p->nx);
     p->visc_L[1] = visc_chunk(p->ny);

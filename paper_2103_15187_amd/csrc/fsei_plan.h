@@ -16,10 +16,11 @@ constexpr int kMaxN = 2048;     // longest x/y transform
 constexpr int kMaxNz = 2048;    // longest z line
 constexpr size_t kAlign = 256;
 constexpr int kSumGroups = 64;   // first-stage workgroups of the two-stage partial sums
-// complex elements per x-transform workgroup (and 8 per thread): small tiles
-// keep several workgroups resident per CU so loads, LDS transforms and
+// complex elements per x-transform workgroup (8 per thread; 256 threads, 384
+// at length 768 so that the tile holds four sequences there too): small
+// tiles keep several workgroups resident per CU so loads, LDS transforms and
 // stores of different workgroups overlap
-inline int x_emax(int) { return 2048; }
+inline int x_emax(int nx) { return nx == 768 ? 3072 : 2048; }
 
 // LDS tile geometry shared by the host (launch sizes) and the kernels:
 // sequence s of length N starts at s * seq_stride(N); one array of a tile of
@@ -120,7 +121,7 @@ struct fsei_plan_impl {
     size_t ws_field2 = 0, ws_field2_bytes = 0;     // second field (refine: FP32 work field)
     size_t ws_field3 = 0, ws_field3_bytes = 0;     // refine: FP64 pressure when the caller passes none
     size_t ws_field4 = 0, ws_field4_bytes = 0;     // refine: FP32 pressure of the first solve
-    size_t ws_list = 0, ws_list_bytes = 0;         // mode lines solved in FP64 by FP32 plans
+    size_t ws_list = 0, ws_list_bytes = 0;         // near-singular mode lines (sequential FP64 solver)
     // implicit viscous step: chunk length per direction (x, y, z; 0 when a
     // line is longer than kViscMaxN), the table blocks of the three
     // components (x, y, z blocks each), and the beta each component's
@@ -133,9 +134,10 @@ struct fsei_plan_impl {
     size_t n_partials = 0;                          // per-block partial sums (triples)
     static constexpr int kScalars = 64;
 
-    // FP32 plans: lines with |lambda_x + lambda_y| < sigma_thr (condition
-    // number above kappa_star) are solved in FP64
+    // lines with |lambda_x + lambda_y| < sigma_thr (condition number above
+    // kappa_star) are solved one per lane in FP64 with row-sum pivots
     double sigma_thr = 0.0;
+    size_t ws_seq = 0;   // FP64 scratch of the near-singular line solver
     std::vector<int> list_host;
     int nlist = 0;
 

@@ -258,7 +258,10 @@ struct Vec2T<float> {
 // x forward: prologue (divergence / transposed gradient / residual / copy)
 // fused with the forward x transform
 // ---------------------------------------------------------------------------
-enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3, PRO_SRC = 4 };
+// RESID: the FP64 residual (f - mean) - L p of an FP64 iterate p; RESID_F: of
+// an FP32 iterate p32 (the first solve of the refinement), read as FP32 and
+// evaluated in FP64
+enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3, PRO_SRC = 4, PRO_RESID_F = 5 };
 
 template <typename TI, typename TO>
 struct XFwdArgs {
@@ -272,6 +275,7 @@ struct XFwdArgs {
     const double* f;    // COPY (double input) and RESID
     const TI* src;      // SRC: input of the prologue's own type
     const double* p;    // RESID
+    const float* p32;   // RESID_F
     TI alpha, beta, idx, idy;
     const TI* zeta;     // coefficient of w_{k+1}
     const TI* eta;      // coefficient of w_k
@@ -283,12 +287,27 @@ struct XFwdArgs {
     TO* out;
     double* out_f;      // optional FP64 copy of the prologue value
     double* partials;   // optional per-block (sum v^2, sum v, sum dzw_k v)
-    const double* dzw;  // with partials: z weights of the third sum (dz_k), or null
+    const double* dzw;  // with partials: z weights of the third sum (dz_k), or null;
+                        // RESID: the third sum is sum dzw_k p (the iterate, not r)
     const TO* twc;
     const TO* tws;
     const TO* dctc;
     const TO* dcts;
 };
+
+// the pressure iterate a residual prologue reads
+template <int PRO, typename TI, typename TO>
+__device__ __forceinline__ auto resid_iterate(const XFwdArgs<TI, TO>& a) {
+    if constexpr (PRO == PRO_RESID_F) return a.p32;
+    else return a.p;
+}
+
+// two adjacent values as a double2 (from double2 or float2)
+__device__ __forceinline__ double2 pair_d(const double* q) { return *reinterpret_cast<const double2*>(q); }
+__device__ __forceinline__ double2 pair_d(const float* q) {
+    const float2 v = *reinterpret_cast<const float2*>(q);
+    return make_double2((double)v.x, (double)v.y);
+}
 
 // The stencil value at cell (k, j, i); `o` is the cell's offset from the
 // workgroup base `base` (first cell of its first row), so all accesses are
@@ -302,20 +321,20 @@ __device__ __forceinline__ TI x_prologue(const XFwdArgs<TI, TO>& a, size_t base,
         return (TI)a.f[base + o];
     } else if constexpr (PRO == PRO_SRC) {
         return a.src[base + o];
-    } else if constexpr (PRO == PRO_RESID) {
-        const double* __restrict__ p = a.p + base;
-        const double pc = p[o];
+    } else if constexpr (PRO == PRO_RESID || PRO == PRO_RESID_F) {
+        const auto* __restrict__ p = resid_iterate<PRO>(a) + base;
+        const double pc = (double)p[o];
         double lx = 0.0, ly = 0.0, lz = 0.0;
-        if (i + 1 < nx) lx += p[o + 1] - pc;
-        else if (a.bcx == FSEI_BC_PERIODIC) lx += p[o + 1 - nx] - pc;
-        if (i >= 1) lx += p[o - 1] - pc;
-        else if (a.bcx == FSEI_BC_PERIODIC) lx += p[o + nx - 1] - pc;
-        if (j + 1 < ny) ly += p[o + nx] - pc;
-        else if (a.bcy == FSEI_BC_PERIODIC) ly += p[o - (ny - 1) * nx] - pc;
-        if (j >= 1) ly += p[o - nx] - pc;
-        else if (a.bcy == FSEI_BC_PERIODIC) ly += p[o + (ny - 1) * nx] - pc;
-        if (k + 1 < nz) lz += a.zc[k] * (p[o + nxy] - pc);
-        if (k >= 1) lz += a.za[k] * (p[o - nxy] - pc);
+        if (i + 1 < nx) lx += (double)p[o + 1] - pc;
+        else if (a.bcx == FSEI_BC_PERIODIC) lx += (double)p[o + 1 - nx] - pc;
+        if (i >= 1) lx += (double)p[o - 1] - pc;
+        else if (a.bcx == FSEI_BC_PERIODIC) lx += (double)p[o + nx - 1] - pc;
+        if (j + 1 < ny) ly += (double)p[o + nx] - pc;
+        else if (a.bcy == FSEI_BC_PERIODIC) ly += (double)p[o - (ny - 1) * nx] - pc;
+        if (j >= 1) ly += (double)p[o - nx] - pc;
+        else if (a.bcy == FSEI_BC_PERIODIC) ly += (double)p[o + (ny - 1) * nx] - pc;
+        if (k + 1 < nz) lz += a.zc[k] * ((double)p[o + nxy] - pc);
+        if (k >= 1) lz += a.za[k] * ((double)p[o - nxy] - pc);
         const double lap = lx * a.idx2 + ly * a.idy2 + lz;
         return (TI)((a.f[base + o] - a.scal[0]) - lap);
     } else {
@@ -333,48 +352,6 @@ __device__ __forceinline__ TI x_prologue(const XFwdArgs<TI, TO>& a, size_t base,
         val *= a.alpha;
         if constexpr (PRO == PRO_DIV_ADJ) {
             if (a.gp) val += a.beta * a.gp[base + o];
-        }
-        return val;
-    }
-}
-
-// The same stencil values on the fixed-length path: `ro` is the offset of the
-// row's first cell (uniform), `rn` its neighbour rows, `cn` the lane's column.
-// Every load is in bounds; absent neighbours are replaced by zero afterwards,
-// so the arithmetic is that of x_prologue.
-template <typename TI, typename TO, int PRO>
-__device__ __forceinline__ TI x_prologue_row(const XFwdArgs<TI, TO>& a, size_t ro, int k, const RowNb& rn,
-                                             const ColNb& cn) {
-    if constexpr (PRO == PRO_COPY) {
-        return (TI)a.f[ro + cn.i];
-    } else if constexpr (PRO == PRO_SRC) {
-        return a.src[ro + cn.i];
-    } else if constexpr (PRO == PRO_RESID) {
-        const double* __restrict__ p = a.p + ro;
-        const double pc = p[cn.i];
-        const double pxp = p[cn.ip], pxm = p[cn.im];
-        const double pyp = (p + rn.yp)[cn.i], pym = (p + rn.ym)[cn.i];
-        const double pzp = (p + rn.zp)[cn.i], pzm = (p + rn.zm)[cn.i];
-        const double fc = a.f[ro + cn.i];
-        const double lx = (cn.hip ? pxp - pc : 0.0) + (cn.him ? pxm - pc : 0.0);
-        const double ly = (rn.hyp ? pyp - pc : 0.0) + (rn.hym ? pym - pc : 0.0);
-        const double lz = (rn.hzp ? a.zc[k] * (pzp - pc) : 0.0) + (rn.hzm ? a.za[k] * (pzm - pc) : 0.0);
-        const double lap = lx * a.idx2 + ly * a.idy2 + lz;
-        return (TI)((fc - a.scal[0]) - lap);
-    } else {
-        const TI zero = (TI)0;
-        const TI* __restrict__ u = a.u + ro;
-        const TI* __restrict__ v = a.v + ro;
-        const TI* __restrict__ w = a.w + ro;
-        const TI uc = u[cn.i], uh = u[cn.ip];
-        const TI vc = v[cn.i], vh = (v + rn.yp)[cn.i];
-        const TI wc = w[cn.i], wh = (w + rn.zp)[cn.i];
-        TI val = ((cn.hip ? uh : zero) - (cn.him ? uc : zero)) * a.idx +
-                 ((rn.hyp ? vh : zero) - (rn.hym ? vc : zero)) * a.idy +
-                 (a.zeta[k] * (rn.hzp ? wh : zero) - a.eta[k] * (rn.hzm ? wc : zero));
-        val *= a.alpha;
-        if constexpr (PRO == PRO_DIV_ADJ) {
-            if (a.gp) val += a.beta * a.gp[ro + cn.i];
         }
         return val;
     }
@@ -411,14 +388,14 @@ __device__ __forceinline__ void x_prologue_pair(const XFwdArgs<TI, TO>& a, size_
         const V q = *reinterpret_cast<const V*>(a.src + ro + cn.i);
         v0 = q.x;
         v1 = q.y;
-    } else if constexpr (PRO == PRO_RESID) {
-        const double* __restrict__ p = a.p + ro;
-        const double2 pc = *reinterpret_cast<const double2*>(p + cn.i);
-        const double pxm = p[cn.im], pxp = p[cn.ip2];
-        const double2 pyp = *reinterpret_cast<const double2*>(p + rn.yp + cn.i);
-        const double2 pym = *reinterpret_cast<const double2*>(p + rn.ym + cn.i);
-        const double2 pzp = *reinterpret_cast<const double2*>(p + rn.zp + cn.i);
-        const double2 pzm = *reinterpret_cast<const double2*>(p + rn.zm + cn.i);
+    } else if constexpr (PRO == PRO_RESID || PRO == PRO_RESID_F) {
+        const auto* __restrict__ p = resid_iterate<PRO>(a) + ro;
+        const double2 pc = pair_d(p + cn.i);
+        const double pxm = (double)p[cn.im], pxp = (double)p[cn.ip2];
+        const double2 pyp = pair_d(p + rn.yp + cn.i);
+        const double2 pym = pair_d(p + rn.ym + cn.i);
+        const double2 pzp = pair_d(p + rn.zp + cn.i);
+        const double2 pzm = pair_d(p + rn.zm + cn.i);
         const double2 fc = *reinterpret_cast<const double2*>(a.f + ro + cn.i);
         const double lx0 = (pc.y - pc.x) + (cn.him ? pxm - pc.x : 0.0);
         const double lx1 = (cn.hip2 ? pxp - pc.y : 0.0) + (pc.x - pc.y);
@@ -490,13 +467,14 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
     const size_t base = (size_t)row0 * N;
     TO* twl = lds_twiddles<TO, NTHR>(a.twc, a.tws, N);
     double* __restrict__ out_f = a.out_f;
-    double ss = 0.0, s1 = 0.0, s2 = 0.0;
+    double ss = 0.0, s1 = 0.0, s2 = 0.0, sp = 0.0;
     if constexpr (NF > 0) {
         static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
         constexpr int CPR = NF / NTHR, NL = 2 * NSF;
         // rows per load batch (the residual stencil loads 8 values per cell:
         // two rows keep its registers within four waves per SIMD)
-        constexpr int RB0 = (PRO == PRO_RESID || (PRO == PRO_DIV && sizeof(TO) == 4)) ? 2 : 4;
+        constexpr bool RES = PRO == PRO_RESID || PRO == PRO_RESID_F;
+        constexpr int RB0 = (RES || (PRO == PRO_DIV && sizeof(TO) == 4)) ? 2 : 4;
         constexpr int RB = (NL % RB0 == 0) ? RB0 : ((NL % 2 == 0) ? 2 : 1);
         // each thread owns the adjacent columns (2q, 2q + 1), q = tid + c NTHR
         constexpr int PPR = CPR / 2;
@@ -520,8 +498,13 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
                 const int l = l0 + lr;
                 const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
 #pragma unroll
-                for (int c = 0; c < PPR; ++c)
+                for (int c = 0; c < PPR; ++c) {
                     x_prologue_pair<TI, TO, PRO>(a, base + (size_t)l * NF, k0, rn, cn[c], val0[lr][c], val1[lr][c]);
+                    if constexpr (RES) {
+                        const double2 pc = pair_d(resid_iterate<PRO>(a) + base + (size_t)l * NF + cn[c].i);
+                        sp += pc.x + pc.y;
+                    }
+                }
             }
 #pragma unroll
             for (int lr = 0; lr < RB; ++lr) {
@@ -538,7 +521,7 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
                 }
             }
         }
-        if (a.dzw) s2 = a.dzw[k0] * s1;   // every row of the tile is in plane k0
+        if (a.dzw) s2 = a.dzw[k0] * (RES ? sp : s1);   // every row of the tile is in plane k0
     } else {
         const int total = nl * N;
         constexpr int PER = 2 * EMAX / NTHR;   // elements per thread, >= total / NTHR
@@ -572,7 +555,8 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
                         if (a.dzw) {
                             int k, j;
                             row_kj(k0, j0, l, a.ny, k, j);
-                            s2 += a.dzw[k] * (double)val[r];
+                            constexpr bool RES = PRO == PRO_RESID || PRO == PRO_RESID_F;
+                            s2 += a.dzw[k] * (RES ? (double)resid_iterate<PRO>(a)[base + e] : (double)val[r]);
                         }
                     }
                     const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
@@ -656,6 +640,8 @@ struct XInvArgs {
     TP* out;
     const float* add32;   // EPI_ADDF: FP32 field added to the result
     T* keep;              // EPI_ACC_KEEP: receives the result (the input field itself)
+    const double* vsum;   // ACC / ADDF: if set, vsum[0] * vscale is subtracted from
+    double vscale;        //   every output (the V-mean of the previous iterate)
     const T* twc;
     const T* tws;
     const T* dctc;
@@ -760,6 +746,7 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
         if constexpr (EPI == EPI_ACC || EPI == EPI_ADDF || EPI == EPI_ACC_KEEP) {
             VP old[NL][PPR];
             const float* __restrict__ add = (EPI == EPI_ADDF) ? a.add32 + base : nullptr;
+            const TP msub = a.vsum ? (TP)(a.vsum[0] * a.vscale) : (TP)0;
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
@@ -767,10 +754,12 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                     const int o = l * NF + 2 * (threadIdx.x + c * NTHR);
                     if constexpr (EPI == EPI_ADDF) {
                         const float2 q = *reinterpret_cast<const float2*>(add + o);
-                        old[l][c].x = (TP)q.x;
-                        old[l][c].y = (TP)q.y;
+                        old[l][c].x = (TP)q.x - msub;
+                        old[l][c].y = (TP)q.y - msub;
                     } else {
                         old[l][c] = *reinterpret_cast<const VP*>(out + o);
+                        old[l][c].x -= msub;
+                        old[l][c].y -= msub;
                     }
                 }
 #pragma unroll
@@ -803,6 +792,7 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
         }
     } else {
         constexpr int PST = 2 * EMAX / NTHR;
+        const TP msub = (EPI != EPI_STORE && a.vsum) ? (TP)(a.vsum[0] * a.vscale) : (TP)0;
 #pragma unroll
         for (int r = 0; r < PST; ++r) {
             const int e = threadIdx.x + r * NTHR;
@@ -812,15 +802,186 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                 if (row0 + l < nrows) {
                     const int n = (a.bcx == FSEI_BC_WALL) ? mk_pos(i, N) : i;
                     const T val = (l & 1) ? sim[li(l >> 1, n, SP)] : sre[li(l >> 1, n, SP)];
-                    if constexpr (EPI == EPI_ACC) out[e] += (TP)val;
-                    else if constexpr (EPI == EPI_ADDF) out[e] = (TP)a.add32[base + e] + (TP)val;
+                    if constexpr (EPI == EPI_ACC) out[e] = (out[e] - msub) + (TP)val;
+                    else if constexpr (EPI == EPI_ADDF) out[e] = ((TP)a.add32[base + e] - msub) + (TP)val;
                     else if constexpr (EPI == EPI_ACC_KEEP) {
-                        out[e] += (TP)val;
+                        out[e] = (out[e] - msub) + (TP)val;
                         a.keep[base + e] = val;
                     } else out[e] = (TP)val;
                 }
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x inverse fused with the gradient correction (paper, Sec. 2.1, eq.
+// NSdiscr0: the pressure term -dt grad p^{n+1} applied to the provisional
+// velocity), FP64, compile-time length NF, one column pair per thread:
+//     p = inverse x transform of the y-inverted field,
+//     u += cx (p_i - p_{i-1}),  v += cy (p_j - p_{j-1}),
+//     w += sw (bk_k p_k - gk_k p_{k-1}),
+// on active faces (wall faces written 0), p written once (optional) and never
+// re-read.  A workgroup owns GR = 8 rows j0..j0+7 over a chunk of planes and
+// marches up in z.  Each step inverts the 8 rows plus row j0-1 (whose p the v
+// update of row j0 needs) of one plane: 9 real rows as 5 complex sequences,
+// the last paired with a zero row.  The own rows' p of the previous plane
+// stay in registers for the w update; the chunk's first step only produces
+// them (it inverts the plane below the chunk).
+// ---------------------------------------------------------------------------
+struct XInvGradArgs {
+    int ny, nz, bcx, bcy, kc;   // kc: planes per chunk
+    const double* in;           // y-inverted field (transform space in x)
+    double* p;                  // pressure out, or null
+    double* u;
+    double* v;
+    double* w;
+    double cx, cy, sw;
+    const double* bk;
+    const double* gk;
+    const double* twc;
+    const double* tws;
+    const double* dctc;
+    const double* dcts;
+};
+
+constexpr int kXgRows = 8;    // own rows per workgroup
+constexpr int kXgSeq = 5;     // complex sequences per step (8 rows + halo + zero row)
+
+// Threads: one per radix-8 butterfly of a stage (5 NF / 8); the first NF / 2
+// also own one column (pair) each in the load and gradient phases.
+template <int NF>
+constexpr int xg_threads() { return kXgSeq * NF / 8; }
+
+template <int NF>
+__global__ __launch_bounds__(xg_threads<NF>()) void k_xinv_grad(XInvGradArgs a) {
+    constexpr int NTHR = xg_threads<NF>();
+    constexpr int GR = kXgRows, NSQ = kXgSeq, EMAX = NSQ * NF;
+    static_assert(NTHR >= NF / 2, "a column pair per thread");
+    constexpr int SP = seq_stride(NF);
+    constexpr int GB = 2;   // rows per batch of the gradient phase
+    static_assert(NSQ * SP <= lds_elems(EMAX), "tile fits");
+    static_assert(2 * NSQ == GR + 2, "halo row + own rows + one zero row");
+    static_assert(GR % GB == 0, "whole batches");
+    __shared__ double sre[lds_elems(EMAX)];
+    __shared__ double sim[lds_elems(EMAX)];
+    const int ny = a.ny, nz = a.nz;
+    const int ntj = ny / GR;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = b / ntj;
+    const int jt = b - chunk * ntj;
+    const int j0 = jt * GR;
+    const int kb = chunk * a.kc;
+    const int ke = (kb + a.kc < nz) ? kb + a.kc : nz;
+    const int jh = (j0 > 0) ? j0 - 1 : ny - 1;   // halo row (wrapped; unused for a y wall at j0 = 0)
+    const bool wallx = a.bcx == FSEI_BC_WALL, wally = a.bcy == FSEI_BC_WALL;
+    double* twl = lds_twiddles<double, NTHR>(a.twc, a.tws, NF);
+    const bool colt = threadIdx.x < NF / 2;   // owns a column (pair)
+    // pre-processing: column m and its partner nm of every row
+    const int m = colt ? threadIdx.x : 0;
+    const int nm = (m == 0) ? NF / 2 : NF - m;
+    const int lm = li(0, m, SP), lnm = li(0, nm, SP);
+    double cm = 1.0, sm = 0.0, cn = 1.0, sn = 0.0;
+    if (wallx) {
+        cm = a.dctc[m];
+        sm = a.dcts[m];
+        cn = (m == 0) ? a.dctc[NF / 2] : sm;
+        sn = (m == 0) ? a.dcts[NF / 2] : cm;
+    }
+    // gradient: this thread's column pair (i, i + 1) and the x neighbour i - 1
+    const int i = 2 * m;
+    const int ixm = (i > 0) ? i - 1 : NF - 1;
+    const int q0 = li(0, wallx ? mk_pos(i, NF) : i, SP);
+    const int q1 = li(0, wallx ? mk_pos(i + 1, NF) : i + 1, SP);
+    const int qm = li(0, wallx ? mk_pos(ixm, NF) : ixm, SP);
+    const size_t plane = (size_t)NF * ny;
+    // input rows of one step: tile row r = 0 is the halo row, r = 1..8 the
+    // own rows, r = 9 zero; sequence s pairs rows 2s and 2s + 1
+    double xa[NSQ][2], xb[NSQ][2];
+    auto load_in = [&](int k) {
+        const double* __restrict__ in = a.in + (size_t)k * plane;
+#pragma unroll
+        for (int s = 0; s < NSQ; ++s) {
+            const int ra = 2 * s, rb = 2 * s + 1;
+            const double* pa = in + (size_t)((ra == 0) ? jh : j0 + ra - 1) * NF;
+            xa[s][0] = pa[m];
+            xa[s][1] = pa[nm];
+            if (rb <= GR) {
+                const double* pb = in + (size_t)(j0 + rb - 1) * NF;
+                xb[s][0] = pb[m];
+                xb[s][1] = pb[nm];
+            } else {
+                xb[s][0] = 0.0;
+                xb[s][1] = 0.0;
+            }
+        }
+    };
+    auto pv = [&](int r, int q) -> double { return ((r & 1) ? sim : sre)[(r >> 1) * SP + q]; };
+    double2 prev[GR];
+#pragma unroll
+    for (int l = 0; l < GR; ++l) prev[l] = make_double2(0.0, 0.0);
+    int k = (kb > 0) ? kb - 1 : 0;
+    for (; k < ke; ++k) {
+        if (colt) load_in(k);
+#pragma unroll
+        for (int s = 0; s < NSQ && colt; ++s) {
+            const double pa = (m == 0) ? xa[s][1] : xa[s][0], pb = (m == 0) ? xb[s][1] : xb[s][0];
+            double zr, zi;
+            pre_inv_cs<double>(NF, m, a.bcx, xa[s][0], xa[s][1], xb[s][0], xb[s][1], cm, sm, zr, zi);
+            sre[s * SP + lm] = zr;
+            sim[s * SP + lm] = zi;
+            pre_inv_cs<double>(NF, nm, a.bcx, xa[s][1], pa, xb[s][1], pb, cn, sn, zr, zi);
+            sre[s * SP + lnm] = zr;
+            sim[s * SP + lnm] = zi;
+        }
+        __syncthreads();
+        fft_lds<double, EMAX, NTHR, 1, NF>(sre, sim, NF, NSQ, FftPlan{}, twl, twl + NF);
+        // the next step's input is in flight during this step's gradient
+        double2 pym = make_double2(pv(0, q0), pv(0, q1));
+        if (!colt) {
+        } else if (k >= kb) {   // not the chunk's first (halo) plane
+            const double bkk = a.bk[k], gkk = a.gk[k];
+            const size_t ro = (size_t)k * plane + (size_t)j0 * NF + i;
+#pragma unroll
+            for (int l0 = 0; l0 < GR; l0 += GB) {
+                double2 uo[GB], vo[GB], wo[GB];
+#pragma unroll
+                for (int t = 0; t < GB; ++t) {
+                    const size_t o = ro + (size_t)(l0 + t) * NF;
+                    uo[t] = *reinterpret_cast<const double2*>(a.u + o);
+                    vo[t] = *reinterpret_cast<const double2*>(a.v + o);
+                    wo[t] = *reinterpret_cast<const double2*>(a.w + o);
+                }
+#pragma unroll
+                for (int t = 0; t < GB; ++t) {
+                    const int l = l0 + t, r = l + 1;
+                    const double2 pc = make_double2(pv(r, q0), pv(r, q1));
+                    const double pxm = pv(r, qm);
+                    const int j = j0 + l;
+                    double2 un, vn, wn;
+                    un.x = (wallx && i == 0) ? 0.0 : uo[t].x + a.cx * (pc.x - pxm);
+                    un.y = uo[t].y + a.cx * (pc.y - pc.x);
+                    const bool v0 = wally && j == 0;
+                    vn.x = v0 ? 0.0 : vo[t].x + a.cy * (pc.x - pym.x);
+                    vn.y = v0 ? 0.0 : vo[t].y + a.cy * (pc.y - pym.y);
+                    wn.x = (k == 0) ? 0.0 : wo[t].x + a.sw * (bkk * pc.x - gkk * prev[l].x);
+                    wn.y = (k == 0) ? 0.0 : wo[t].y + a.sw * (bkk * pc.y - gkk * prev[l].y);
+                    const size_t o = ro + (size_t)l * NF;
+                    *reinterpret_cast<double2*>(a.u + o) = un;
+                    *reinterpret_cast<double2*>(a.v + o) = vn;
+                    *reinterpret_cast<double2*>(a.w + o) = wn;
+                    if (a.p) *reinterpret_cast<double2*>(a.p + o) = pc;
+                    prev[l] = pc;
+                    pym = pc;
+                }
+                // keep the next batch's loads after this batch's stores
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int l = 0; l < GR; ++l) prev[l] = make_double2(pv(l + 1, q0), pv(l + 1, q1));
+        }
+        __syncthreads();   // the next step overwrites the tile
     }
 }
 

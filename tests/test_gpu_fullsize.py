@@ -1,12 +1,14 @@
 """GPU checks at the full workload sizes, in the launch configuration the
 benchmark times (library defaults).
 
-At 512x512x768 the oracle cannot produce the whole answer in seconds, so the
-FP64 projection is checked (a) on sampled outputs the oracle computes one by
-one: individual (kx, ky) mode lines of p (the oracle transforms f onto that
-mode with its dense matrix rows and solves that one tridiagonal), and (b) on
-properties that hold at any size (discrete divergence of the result, V-mean of
-p, the residual of the Poisson equation computed on the host)."""
+At 512x512x768 the whole projection is compared with the oracle's whole-field
+result (about a minute on the host).  Both there and at 768x768x1024 (where
+only sampled outputs are computed) the FP64 result is also checked (a) on
+sampled outputs computed one by one: individual (kx, ky) mode lines of p (the
+transform rows applied to f and that one tridiagonal solved, in FP64 and in
+long double), and (b) on properties that hold at any size (discrete divergence
+of the result, V-mean of p, the residual of the Poisson equation computed on
+the host)."""
 import numpy as np
 import pytest
 
@@ -40,6 +42,53 @@ def mode_line(field, mx_row, my_row):
     return (field @ mx_row) @ my_row
 
 
+class LineReference:
+    """Sampled (kx, ky) mode lines of p = L^+ f, computed one by one: the
+    transform rows applied to f and one Thomas solve, both in FP64 (the
+    oracle's arithmetic) and in long double (the reference both FP64 results
+    are measured against).  A sampled line of the GPU result passes when its
+    error against the long-double line is at most 1e-12 of the larger of
+    the line's norm and the root-mean-square norm of all lines (||p||_F / 2
+    by Parseval for these transform rows, whose squared norms are n/2: the
+    whole-field 1e-12 bar spread evenly over the lines), or at most twice the
+    FP64 oracle's own error on that line (the line's FP64 floor; at the
+    lowest modes, condition ~1e7-1e8, that floor is above 1e-12)."""
+
+    def __init__(self, f, g, spec):
+        self.g, self.spec = g, spec
+        self.f = f
+        self.fl = f.astype(np.longdouble)
+        self.M = {ld: (oracle.transform_matrix(spec.nx, spec.bcx, np.longdouble if ld else np.float64),
+                       oracle.transform_matrix(spec.ny, spec.bcy, np.longdouble if ld else np.float64))
+                  for ld in (False, True)}
+        self.lam = {ld: (oracle.eigenvalues(spec.nx, spec.dx, spec.bcx, np.longdouble if ld else np.float64),
+                         oracle.eigenvalues(spec.ny, spec.dy, spec.bcy, np.longdouble if ld else np.float64))
+                    for ld in (False, True)}
+        self.zc = {ld: oracle.z_coefficients(g, np.longdouble if ld else np.float64) for ld in (False, True)}
+
+    def line(self, qx, qy, ld):
+        Mx, My = self.M[ld]
+        lx, ly = self.lam[ld]
+        a, c = self.zc[ld]
+        fh = mode_line(self.fl if ld else self.f, Mx[qx], My[qy])
+        b = -(a + c) + (lx[qx] + ly[qy])
+        return oracle.thomas(a, b[:, None], c, fh[:, None])[:, 0]
+
+    def check(self, p, qx, qy, tag=""):
+        ref = self.line(qx, qy, True)
+        ph64 = self.line(qx, qy, False)
+        Mx, My = self.M[True]
+        ph_gpu = mode_line(p.astype(np.longdouble), Mx[qx], My[qy])
+        nrm = float(np.linalg.norm(ref))
+        rms = 0.5 * float(np.linalg.norm(p))
+        err = float(np.linalg.norm(ph_gpu - ref)) / nrm
+        err64 = float(np.linalg.norm(ph64 - ref)) / nrm
+        print(f"{tag} mode ({qx},{qy}) rel err {err:.2e} (FP64 oracle line {err64:.2e}; "
+              f"line norm / rms {nrm / rms:.2e})", flush=True)
+        assert err <= max(1e-12 * max(1.0, rms / nrm), 2.0 * err64), (qx, qy, err, err64)
+        return err
+
+
 @pytest.fixture(scope="module")
 def c3():
     spec = W.CONFIGS["C3"]
@@ -47,6 +96,7 @@ def c3():
     return spec, u, v, w
 
 
+@pytest.mark.timeout(600)
 def test_c3_fp64_sampled_modes_and_properties(c3):
     spec, u, v, w = c3
     g = grid_of(spec)
@@ -57,23 +107,13 @@ def test_c3_fp64_sampled_modes_and_properties(c3):
     torch.cuda.synchronize()
     p = p_d.cpu().numpy()
     f = oracle.divergence(u, v, w, g)
-    # (a) sampled mode lines against the oracle's own transform rows + Thomas
+    # (a) sampled mode lines against long-double lines (see LineReference)
+    ref = LineReference(f, g, spec)
+    for qx, qy in [(1, 0), (0, 1), (1, 1), (3, 7), (37, 200), (255, 256), (511, 511), (0, 511), (2, 0)]:
+        ref.check(p, qx, qy, "C3 fp64")
+    del ref
     Mx = oracle.transform_matrix(spec.nx, spec.bcx)
     My = oracle.transform_matrix(spec.ny, spec.bcy)
-    lx = oracle.eigenvalues(spec.nx, spec.dx, spec.bcx)
-    ly = oracle.eigenvalues(spec.ny, spec.dy, spec.bcy)
-    a, c = oracle.z_coefficients(g)
-    dzmin = g.dz.min()
-    for qx, qy in [(1, 0), (0, 1), (1, 1), (3, 7), (37, 200), (255, 256), (511, 511), (0, 511), (2, 0)]:
-        fh = mode_line(f, Mx[qx], My[qy])
-        sigma = lx[qx] + ly[qy]
-        b = -(a + c) + sigma
-        ph_ref = oracle.thomas(a, b[:, None], c, fh[:, None])[:, 0]
-        ph_gpu = mode_line(p, Mx[qx], My[qy])
-        kappa = 1.0 + 4.0 / (dzmin ** 2 * abs(sigma))
-        err = np.linalg.norm(ph_gpu - ph_ref) / np.linalg.norm(ph_ref)
-        print(f"mode ({qx},{qy}) kappa={kappa:.2e} rel err {err:.2e}")
-        assert err <= 1e-12 + 4e-16 * kappa * 100
     # (0,0) mode: dz-weighted mean of the line is the V-mean of p -> zero
     p00 = mode_line(p, Mx[0], My[0])
     assert abs((g.dz * p00).sum()) <= 1e-13 * np.abs(p00).max() * g.dz.sum()
@@ -101,6 +141,43 @@ def test_c3_fp32_refine_residual(c3):
     assert oracle.rel_residual(f, p, g) <= 1e-10
     un, vn, wn = ud.cpu().numpy(), vd.cpu().numpy(), wd.cpu().numpy()
     assert np.abs(oracle.divergence(un, vn, wn, g)).max() <= 1e-9 * np.abs(f).max()
+
+
+@pytest.fixture(scope="module")
+def c3_oracle(c3):
+    """The oracle's whole projection of the 512x512x768 input (about a
+    minute on the host)."""
+    spec, u, v, w = c3
+    return oracle.project(u, v, w, grid_of(spec))
+
+
+@pytest.mark.timeout(900)
+def test_c3_full_field_vs_oracle(c3, c3_oracle):
+    """Every output of the 512x512x768 projection against the oracle's
+    whole-field result, FP64 and FP32+refine, in the benchmark's launch
+    configuration.  FP64: relative L2 <= 1e-12 for u, v, w and p (both p
+    V-mean pinned).  FP32+refine: the residual reaches 1e-10; its error
+    against the oracle is printed and bounded by the residual's forward
+    error (see the bars below)."""
+    spec, u, v, w = c3
+    ru, rv, rw, rp = c3_oracle
+    F = fsei()
+    errs = {}
+    for name, kw in (("fp64", {}), ("fp32_refine", dict(precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=4))):
+        plan = F.Plan.from_spec(spec, **kw)
+        ud, vd, wd = to_dev(u), to_dev(v), to_dev(w)
+        p_d, info = plan.project(ud, vd, wd, info=True)
+        torch.cuda.synchronize()
+        e = {k: rel(t.cpu().numpy(), r) for k, t, r in (("u", ud, ru), ("v", vd, rv), ("w", wd, rw), ("p", p_d, rp))}
+        errs[name] = e
+        print(f"C3 {name}: info {info}; rel L2 vs oracle " + ", ".join(f"{k} {x:.3e}" for k, x in e.items()),
+              flush=True)
+        del plan, ud, vd, wd, p_d
+        torch.cuda.empty_cache()
+    assert max(errs["fp64"].values()) <= 1e-12, errs["fp64"]
+    # refinement to a 1e-10 residual: p (V-mean pinned in FP64) and u within
+    # the residual's level of the oracle
+    assert max(errs["fp32_refine"].values()) <= 1e-10, errs["fp32_refine"]
 
 
 def test_c2_fp64_solve_full_oracle():
@@ -184,7 +261,7 @@ def test_c4b_fp32_gradient_vs_fp64_oracle():
     assert max(errs) <= 1e-5
 
 
-@pytest.mark.timeout(400)
+@pytest.mark.timeout(900)
 def test_c5_fp64_modes_and_refine_to_fp64_floor():
     """768x768x1024 walls, tanh 3.0, power-law right-hand side (radix-3
     lengths: the generic transform path; nz = 1024).
@@ -206,21 +283,12 @@ def test_c5_fp64_modes_and_refine_to_fp64_floor():
     F = fsei()
     fd = to_dev(f)
     p64 = F.Plan.from_spec(spec).poisson_solve(fd).cpu().numpy()
+    ref = LineReference(f, g, spec)
+    for qx, qy in [(1, 0), (0, 1), (5, 3), (63, 17), (40, 63), (2, 2)]:
+        ref.check(p64, qx, qy, "C5 fp64")
+    del ref
     Mx = oracle.transform_matrix(spec.nx, spec.bcx)
     My = oracle.transform_matrix(spec.ny, spec.bcy)
-    lx = oracle.eigenvalues(spec.nx, spec.dx, spec.bcx)
-    ly = oracle.eigenvalues(spec.ny, spec.dy, spec.bcy)
-    a, c = oracle.z_coefficients(g)
-    dzmin = g.dz.min()
-    for qx, qy in [(1, 0), (0, 1), (5, 3), (63, 17), (40, 63), (2, 2)]:
-        fh = mode_line(f, Mx[qx], My[qy])
-        sigma = lx[qx] + ly[qy]
-        ph_ref = oracle.thomas(a, (-(a + c) + sigma)[:, None], c, fh[:, None])[:, 0]
-        ph_gpu = mode_line(p64, Mx[qx], My[qy])
-        kappa = 1.0 + 4.0 / (dzmin ** 2 * abs(sigma))
-        err = np.linalg.norm(ph_gpu - ph_ref) / np.linalg.norm(ph_ref)
-        print(f"C5 fp64 mode ({qx},{qy}) kappa={kappa:.2e} rel err {err:.2e}")
-        assert err <= 1e-12 + 4e-16 * kappa * 100
     floor64 = oracle.rel_residual(f, p64, g)
     del p64
     plan = F.Plan.from_spec(spec, precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6, accept_floor=True)
@@ -233,9 +301,8 @@ def test_c5_fp64_modes_and_refine_to_fp64_floor():
     assert abs(info["rel_residual"] - res) <= 0.05 * res
     assert 1 <= info["iterations"] <= 6
     assert info["floor_reached"] == (info["rel_residual"] > 1e-10)
-    # the residual is blind to constants (the null space of L), so the
-    # refinement never corrects the V-mean of p: it stays pinned by the first
-    # FP32 solve, i.e. to FP32 rounding of p
+    # the residual is blind to constants (the null space of L); the first
+    # correction pins the V-mean of p in FP64 instead
     vmean_p = (g.dz * mode_line(p, Mx[0], My[0])).sum() / (g.dz.sum() * spec.nx * spec.ny)
     print(f"C5 refine V-mean of p {vmean_p:.3e} (max |p| {np.abs(p).max():.3e})")
-    assert abs(vmean_p) <= 1.2e-7 * np.abs(p).max()
+    assert abs(vmean_p) <= 1e-13 * np.abs(p).max()
