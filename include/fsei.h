@@ -32,8 +32,12 @@
  * Execution: every call enqueues kernels on the plan's stream and returns
  * without waiting, except (a) when an fsei_info pointer is passed (the call
  * then waits for the stream to read back scalars) and (b) FP32_REFINE with
- * rtol > 0 (one scalar is read back per refinement iteration).  A plan is not
- * thread-safe; calls that share a plan must be serialised by the caller.
+ * rtol > 0 (one scalar is read back per refinement iteration).  Inside the z
+ * solve the plan forks to a side stream of its own (created on the current
+ * device by fsei_plan_set_workspace, destroyed with the plan) and joins it
+ * with events before the next step, so work stays ordered on the plan's
+ * stream.  A plan is not thread-safe; calls that share a plan must be
+ * serialised by the caller.
  *
  * Errors: arguments are checked before anything is launched; no C++
  * exception crosses this interface.  A failing HIP call is reported as
@@ -111,8 +115,9 @@ fsei_status fsei_plan_workspace_size(const fsei_plan* plan, size_t* bytes);
 
 /* Hand the plan a device buffer of at least fsei_plan_workspace_size bytes,
  * 256-byte aligned.  Uploads the metric, eigenvalue and twiddle tables with a
- * synchronous copy.  The buffer stays owned by the caller and must outlive its
- * use by the plan. */
+ * synchronous copy, and on the first call creates the plan's side stream and
+ * two events on the current device (see Execution above).  The buffer stays
+ * owned by the caller and must outlive its use by the plan. */
 fsei_status fsei_plan_set_workspace(fsei_plan* plan, void* device_ptr, size_t bytes);
 
 /* Stream (a hipStream_t passed as void*) on which all work is enqueued. NULL =

@@ -212,16 +212,32 @@ def _apply_along(M, a, axis):
 
 
 def _solve_along(M, a, axis):
-    """Apply M^{-1} along `axis`, via a linear solve with M."""
+    """Apply M^{-1} along `axis`: a linear solve with M in FP64; in long
+    double the closed-form inverse (numpy's LAPACK path has no long-double
+    solver, and elimination in Python loops is O(n^3) per call)."""
     a = np.moveaxis(a, axis, 0)
     shp = a.shape
-    x = np.linalg.solve(M, a.reshape(shp[0], -1)) if M.dtype != np.longdouble else _ld_solve(M, a.reshape(shp[0], -1))
+    if M.dtype != np.longdouble:
+        x = np.linalg.solve(M, a.reshape(shp[0], -1))
+    else:
+        x = inverse_closed_form(M) @ a.reshape(shp[0], -1)
     return np.moveaxis(x.reshape(shp), 0, axis)
+
+
+def inverse_closed_form(M):
+    """M^{-1} = M^T diag(1 / ||row_q||^2) for the transform matrices of
+    transform_matrix: their rows are mutually orthogonal (the DCT-II rows,
+    and the cosine and sine rows of the real DFT), with squared norms n for
+    the constant row and the periodic Nyquist row and n/2 for every other."""
+    n = M.shape[0]
+    w = np.einsum("qi,qi->q", M, M)
+    return M.T * (1 / w)[None, :]
 
 
 def _ld_solve(M, B):
     """Gaussian elimination with partial pivoting in long double (numpy's
-    LAPACK path has no long-double solver)."""
+    LAPACK path has no long-double solver); the reference the closed-form
+    inverse is pinned against."""
     n = M.shape[0]
     A = M.copy()
     X = B.copy()
@@ -335,20 +351,21 @@ def project(u, v, w, g: Grid, dt=1.0, dtype=np.float64):
     return un, vn, wn, p
 
 
-def project_adjoint(gu, gv, gw, gp, g: Grid, dt=1.0):
+def project_adjoint(gu, gv, gw, gp, g: Grid, dt=1.0, dtype=np.float64):
     """Adjoint of `project` with respect to u*.  With V D = -G^T W
     (summation by parts), P = I - G L^+ D satisfies P^T = W P W^{-1} and
     (L^+)^T = V L^+ V^{-1}, so
 
         g_u* = W P (W^-1 g_u) - (1/dt) W G L^+ (V^-1 g_p).
 
-    This uses only the oracle's own forward operators."""
+    This uses only the oracle's own forward operators (their solves in
+    `dtype`)."""
     wu, wv, ww = g.face_weights()
     xu, xv, xw = _zero_dead(gu / wu, gv / wv, gw / ww, g)
-    pu, pv, pw, _ = project(xu, xv, xw, g, dt=1.0)
+    pu, pv, pw, _ = project(xu, xv, xw, g, dt=1.0, dtype=dtype)
     ou, ov, ow = wu * pu, wv * pv, ww * pw
     if gp is not None:
-        s = poisson_solve(gp / g.cell_volume(), g)
+        s = poisson_solve(gp / g.cell_volume(), g, dtype=dtype)
         sx, sy, sz = gradient(s, g)
         ou = ou - wu * sx / dt
         ov = ov - wv * sy / dt

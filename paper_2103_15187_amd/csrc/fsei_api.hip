@@ -79,23 +79,26 @@ void harvest(fsei_plan* p) {
     ts.pending.clear();
 }
 
-// Brackets one launch with events when timing is on.
+// Brackets one launch with events when timing is on (on the stream the
+// launch goes to: the plan's, or its side stream).
 struct Timed {
     fsei_plan* p;
     int slot;
+    hipStream_t st;
     hipEvent_t a = nullptr, b = nullptr;
-    Timed(fsei_plan* pl, int s) : p(pl), slot(s) {
+    Timed(fsei_plan* pl, int s, void* stream = nullptr)
+        : p(pl), slot(s), st((hipStream_t)(stream ? stream : pl->stream)) {
         if (p->timing) {
             TimingState& ts = tstate(p);
             if (ts.pending.size() > 4096) harvest(p);
             a = get_event(ts);
             b = get_event(ts);
-            (void)hipEventRecord(a, (hipStream_t)p->stream);
+            (void)hipEventRecord(a, st);
         }
     }
     ~Timed() {
         if (p->timing) {
-            (void)hipEventRecord(b, (hipStream_t)p->stream);
+            (void)hipEventRecord(b, st);
             tstate(p).pending.push_back({a, b, slot});
         }
     }
@@ -160,7 +163,7 @@ void launch_xfwd(fsei_plan* p, XFwdArgs<TI, TO> a, int slot) {
     a.dcts = tab<TO>(p, T_DCTX_S);
     const size_t dyn = 2 * p->nx * sizeof(TO);
     // the fixed path reads and writes every field as aligned column pairs
-    const bool al = al16(a.u) && al16(a.v) && al16(a.w) && al16(a.gp) && al16(a.f) && al16(a.src) && al16(a.p) &&
+    const bool al = al16(a.u) && al16(a.v) && al16(a.w) && al16(a.gp) && al16(a.f) && al16(a.p) &&
                     al16(a.p32) && al16(a.out) && al16(a.out_f);
     Timed t(p, slot);
     const dim3 grid((unsigned)xblocks(p));
@@ -215,13 +218,9 @@ bool xg_ok(const fsei_plan* p, const void* in, const void* pout, const void* u, 
            aligned16(u) && aligned16(v) && aligned16(w);
 }
 
-int xg_planes() {
-    static int v = [] {
-        const char* e = getenv("FSEI_XG_KC");
-        return e ? atoi(e) : 16;
-    }();
-    return v;
-}
+// planes per workgroup of the fused x inverse + gradient (the chunk's first
+// step re-inverts the plane below it: 1/32 more transform work)
+constexpr int kXgPlanes = 32;
 
 void launch_xinv_grad(fsei_plan* p, const double* in, double* pout, double* u, double* v, double* w,
                       bool adjoint, double dt) {
@@ -230,7 +229,7 @@ void launch_xinv_grad(fsei_plan* p, const double* in, double* pout, double* u, d
     a.nz = p->nz;
     a.bcx = p->bcx;
     a.bcy = p->bcy;
-    a.kc = xg_planes();
+    a.kc = kXgPlanes;
     a.in = in;
     a.p = pout;
     a.u = u;
@@ -301,13 +300,16 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     }
 }
 
-// Compile-time length 768 in y: tiles of 128-byte row segments (8 FP64 /
-// 16 FP32 column pairs) in 768-thread workgroups; needs whole tiles and
-// pair-aligned data.  Returns false where it does not apply.
+// Compile-time length 768 in y: tiles of 64-byte row segments (4 FP64 /
+// 8 FP32 column pairs) in 768-thread workgroups, two workgroups per CU
+// (measured at 768 x 768 x 1024: 5-12 % faster than one workgroup of
+// 128-byte segments per CU, whose 105 KB tile leaves no second one room);
+// needs whole tiles and pair-aligned data.  Returns false where it does not
+// apply.
 template <typename T>
 bool launch_y768(fsei_plan* p, YArgs<T> a, bool inverse) {
     constexpr int NF = 768, NTHR = 768;
-    constexpr int EMAX = (64 / (int)sizeof(T)) * NF;   // 128-B tile rows
+    constexpr int EMAX = (32 / (int)sizeof(T)) * NF;   // 64-B tile rows
     constexpr int kPsF = yfwd_pad<T>();
     static_assert(y_fixed_ok(EMAX, NTHR, NF) && y_fixed_ok(EMAX, NTHR, NF, kPsF) &&
                       tile_nseq(EMAX, NF, kPsF) == tile_nseq(EMAX, NF) && tile_nseq(EMAX, NF) == EMAX / NF,
@@ -435,6 +437,14 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
     // FP32 chunks of at most 16 rows, which avoids register spills.
     int L = 0, P = 0;
     const bool c32 = choose_chunks(nz, 32, &L, &P);
+    // The near-singular lines and the (0,0) line are disjoint from the lines
+    // of the tiled kernel: they run on the plan's side stream (when it has
+    // one), concurrently with it, joined before the next step.
+    hipStream_t side = p->side_stream ? (hipStream_t)p->side_stream : S(p);
+    if (p->side_stream) {
+        (void)hipEventRecord((hipEvent_t)p->ev_fork, S(p));
+        (void)hipStreamWaitEvent(side, (hipEvent_t)p->ev_fork, 0);
+    }
     if constexpr (!F32) {
         ZArgs<double, double> a = zargs<double, double>(p, data, transposed);
         a.sigma_thr = p->sigma_thr;   // the host's threshold, compared in FP64
@@ -495,8 +505,8 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         b.lamy = tab<double>(p, T_LAMY);
         b.dz = tab<double>(p, T_DZ);
         b.scale = 1.0 / ((double)p->nx * (double)p->ny);
-        Timed t(p, K_ZLIST);
-        hipLaunchKernelGGL((k_zline_seq<TS>), dim3((unsigned)((p->nlist + 63) / 64)), dim3(64), 0, S(p), b);
+        Timed t(p, K_ZLIST, side);
+        hipLaunchKernelGGL((k_zline_seq<TS>), dim3((unsigned)((p->nlist + 63) / 64)), dim3(64), 0, side, b);
     }
     ZeroArgs<TS> z{};
     z.nz = nz;
@@ -509,8 +519,14 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
     z.inv_dz = tab<double>(p, T_INV_DZ);
     z.h = tab<double>(p, T_H);
     z.scal = record_mean ? scalars(p) : nullptr;
-    Timed t(p, K_PREP);
-    hipLaunchKernelGGL((k_zero_mode<TS>), dim3(1), dim3(256), 0, S(p), z);
+    {
+        Timed t(p, K_PREP, side);
+        hipLaunchKernelGGL((k_zero_mode<TS>), dim3(1), dim3(256), 0, side, z);
+    }
+    if (p->side_stream) {
+        (void)hipEventRecord((hipEvent_t)p->ev_join, side);
+        (void)hipStreamWaitEvent(S(p), (hipEvent_t)p->ev_join, 0);
+    }
 }
 
 // k_grad_row2 with the smallest workgroup that gives every cell pair of a
@@ -570,10 +586,10 @@ void launch_grad(fsei_plan* p, TIO* u, TIO* v, TIO* w, const TP* pr, bool adjoin
     hipLaunchKernelGGL((k_grad<TIO, TP>), dim3((unsigned)((long)p->ny * p->nz)), dim3(256), 0, S(p), a);
 }
 
-// FP64 residual pass of the refinement (partials of sum r^2, sum r; with
-// out32, also r in FP32); returns the number of partials written
+// FP64 residual norm pass of the refinement (partials of sum r^2, sum r,
+// sum dz_k p); returns the number of partials written
 template <typename TPP>
-long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr, float* out32) {
+long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr) {
     ResArgs<TPP> a{};
     a.nx = p->nx;
     a.ny = p->ny;
@@ -589,30 +605,18 @@ long launch_resid_pairs(fsei_plan* p, const double* f, const TPP* pr, float* out
     a.scal = scalars(p);
     a.dz = tab<double>(p, T_DZ);
     a.partials = partials(p);
-    a.out = out32;
     const long nb = (long)(p->ny / kPairRows) * p->nz;
     const dim3 grid((unsigned)nb);
     const int np = p->nx / 2;
-    Timed t(p, out32 ? K_RESID_PAIRS : K_RESNORM);
-    if (out32) {
-        if (np == 384)
-            hipLaunchKernelGGL((k_resid_pairs<384, kPairRows, true, TPP>), grid, dim3(384), 0, S(p), a);
-        else if (np >= 256)
-            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, true, TPP>), grid, dim3(256), 0, S(p), a);
-        else if (np > 64)
-            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, true, TPP>), grid, dim3(128), 0, S(p), a);
-        else
-            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, true, TPP>), grid, dim3(64), 0, S(p), a);
-    } else {
-        if (np == 384)
-            hipLaunchKernelGGL((k_resid_pairs<384, kPairRows, false, TPP>), grid, dim3(384), 0, S(p), a);
-        else if (np >= 256)
-            hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, false, TPP>), grid, dim3(256), 0, S(p), a);
-        else if (np > 64)
-            hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, false, TPP>), grid, dim3(128), 0, S(p), a);
-        else
-            hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, false, TPP>), grid, dim3(64), 0, S(p), a);
-    }
+    Timed t(p, K_RESNORM);
+    if (np == 384)
+        hipLaunchKernelGGL((k_resid_pairs<384, kPairRows, TPP>), grid, dim3(384), 0, S(p), a);
+    else if (np >= 256)
+        hipLaunchKernelGGL((k_resid_pairs<256, kPairRows, TPP>), grid, dim3(256), 0, S(p), a);
+    else if (np > 64)
+        hipLaunchKernelGGL((k_resid_pairs<128, kPairRows, TPP>), grid, dim3(128), 0, S(p), a);
+    else
+        hipLaunchKernelGGL((k_resid_pairs<64, kPairRows, TPP>), grid, dim3(64), 0, S(p), a);
     return nb;
 }
 
@@ -893,44 +897,31 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         floor = !converged && rel_prev >= 0.0 && rel > 0.5 * rel_prev;
         return FSEI_OK;
     };
-    // residual of the first solve, transformed for the first correction
-    // Residual passes.  With the pair tiling: the FP64 residual kernel
-    // (norm partials, and r in FP32 when a correction follows) plus an FP32
-    // x transform of r in place; otherwise the x-forward kernel with the
-    // residual stencil as its prologue (no output for a norm-only pass).
+    // Residual passes.  A pass that feeds a correction is the x-forward
+    // kernel with the FP64 residual stencil as its prologue (reading the FP32
+    // first solve, or the FP64 iterate), writing the FP32 transform of r and
+    // the partial sums; a norm-only pass is the pair residual kernel (with
+    // the pair tiling) or the same x-forward prologue without output.
     auto norm_pass = [&]() {
         if (pairs) {
-            nres = p_in_32 ? launch_resid_pairs(p, f64, (const float*)p32, nullptr)
-                           : launch_resid_pairs(p, f64, (const double*)p64, nullptr);
+            nres = p_in_32 ? launch_resid_pairs(p, f64, (const float*)p32)
+                           : launch_resid_pairs(p, f64, (const double*)p64);
         } else {
             r.out = nullptr;
             nres = -1;
             launch_xfwd<double, float, PRO_RESID>(p, r, K_RESNORM);
         }
     };
-    static const bool fused_resid = getenv("FSEI_RESID_FUSED") != nullptr;
     auto resid_pass = [&]() {
-        if (fused_resid && p_in_32) {
+        nres = -1;
+        if (p_in_32) {
             XFwdArgs<double, float> r32 = r;
             r32.p = nullptr;
             r32.p32 = p32;
             r32.out = w32;
-            nres = -1;
             launch_xfwd<double, float, PRO_RESID_F>(p, r32, K_RESID_XFWD);
-        } else if (fused_resid) {
-            r.out = w32;
-            nres = -1;
-            launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
-        } else if (pairs) {
-            nres = p_in_32 ? launch_resid_pairs(p, f64, (const float*)p32, w32)
-                           : launch_resid_pairs(p, f64, (const double*)p64, w32);
-            XFwdArgs<float, float> t{};
-            t.src = w32;
-            t.out = w32;
-            launch_xfwd<float, float, PRO_SRC>(p, t, K_XFWD_R);
         } else {
             r.out = w32;
-            nres = -1;
             launch_xfwd<double, float, PRO_RESID>(p, r, K_RESID_XFWD);
         }
     };
@@ -1029,6 +1020,11 @@ void fsei_poisson_plan_destroy(fsei_plan* p) {
         for (auto e : ts->free_ev) (void)hipEventDestroy(e);
         delete ts;
     }
+    if (p->side_stream) {
+        (void)hipStreamDestroy((hipStream_t)p->side_stream);
+        (void)hipEventDestroy((hipEvent_t)p->ev_fork);
+        (void)hipEventDestroy((hipEvent_t)p->ev_join);
+    }
     delete p;
 }
 
@@ -1051,6 +1047,24 @@ fsei_status fsei_plan_set_workspace(fsei_plan* p, void* dev, size_t bytes) {
     p->ws = dev;
     p->ws_bytes = bytes;
     for (double& b : p->visc_beta) b = 0.0;   // viscous tables live in the workspace: rebuild on next use
+    if (!p->side_stream) {
+        // side stream (default priority) and the fork / join events of the z
+        // solve; without them everything runs on the plan's stream
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&e0, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess) {
+            p->side_stream = st;
+            p->ev_fork = e0;
+            p->ev_join = e1;
+        } else {
+            if (st) (void)hipStreamDestroy(st);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            (void)hipGetLastError();
+        }
+    }
     return FSEI_OK;
 }
 

@@ -484,75 +484,92 @@ struct ZSeqArgs {
 
 template <typename TS>
 __global__ __launch_bounds__(64) void k_zline_seq(ZSeqArgs<TS> a) {
-    // Rows go in batches of B; the next batch's loads are issued before the
-    // current batch is eliminated, so memory latency overlaps the sweep.
-    constexpr int B = 32;
+    // The per-row coefficients go to LDS first (uniform reads there, off the
+    // critical path of the recurrences).  Rows go in batches of B with the
+    // next batch's loads issued before the current batch is eliminated; the
+    // batch bodies have no branches (row indices of loads are clamped into
+    // the line, and the last nz % B rows are a separate tail), so the
+    // compiler waits only for the batch it uses.
+    constexpr int B = 16;
+    __shared__ double sa[kMaxNz], sc[kMaxNz], si[kMaxNz], so[kMaxNz];
+    const int nz = a.nz, nl = a.nlist;
+    for (int k = threadIdx.x; k < nz; k += 64) {
+        sa[k] = (k > 0) ? a.za[k] : 0.0;
+        sc[k] = (k + 1 < nz) ? a.zc[k] : 0.0;
+        si[k] = a.transposed ? a.scale / a.dz[k] : a.scale;
+        so[k] = a.transposed ? a.dz[k] : 1.0;
+    }
+    __syncthreads();
     const int li = blockIdx.x * 64 + threadIdx.x;
-    if (li >= a.nlist) return;
+    if (li >= nl) return;
     const int line = a.list[li];
     const int qy = line / a.nx, qx = line - qy * a.nx;
     const double sigma = a.lamx[qx] + a.lamy[qy];
     const TS* __restrict__ colr = a.data + line;
-    const int nz = a.nz, nl = a.nlist;
+    TS* __restrict__ colw = a.data + line;
     const size_t st = a.stride;
     double* __restrict__ ys = a.ys + li;
     double* __restrict__ cps = a.cps + li;
+    const int nfull = nz - nz % B;
     auto load_rows = [&](int k0, double* f) {
 #pragma unroll
         for (int t = 0; t < B; ++t) {
-            const int k = k0 + t;
-            f[t] = (k < nz) ? (double)colr[(size_t)k * st] : 0.0;
+            const int k = (k0 + t < nz) ? k0 + t : nz - 1;   // clamped (the value is then unused)
+            f[t] = (double)colr[(size_t)k * st];
         }
     };
     double q = 1.0, y = 0.0;   // q = g_{k-1} / d_{k-1} (1 before the first row)
+    auto fwd_row = [&](int k, double f) {
+        const double A = sa[k], C = sc[k];
+        const double g = sigma - A * q;
+        const double r = zrcp(g - C);
+        q = g * r;
+        y = (f * si[k] - A * y) * r;
+        ys[(size_t)k * nl] = y;
+        cps[(size_t)k * nl] = C * r;
+    };
     double fa[B], fb[B];
     load_rows(0, fa);
-    for (int k0 = 0; k0 < nz; k0 += B) {
-        if (k0 + B < nz) load_rows(k0 + B, fb);
+    for (int k0 = 0; k0 < nfull; k0 += B) {
+        load_rows(k0 + B, fb);
 #pragma unroll
-        for (int t = 0; t < B; ++t) {
-            const int k = k0 + t;
-            if (k < nz) {
-                const double A = (k > 0) ? a.za[k] : 0.0, C = (k + 1 < nz) ? a.zc[k] : 0.0;
-                const double fs = fa[t] * (a.transposed ? a.scale / a.dz[k] : a.scale);
-                const double g = sigma - A * q;
-                const double d = g - C;
-                q = g / d;
-                y = (fs - A * y) / d;
-                ys[(size_t)k * nl] = y;
-                cps[(size_t)k * nl] = C / d;
-            }
-        }
+        for (int t = 0; t < B; ++t) fwd_row(k0 + t, fa[t]);
 #pragma unroll
         for (int t = 0; t < B; ++t) fa[t] = fb[t];
     }
-    TS* __restrict__ colw = a.data + line;
-    auto load_back = [&](int k1, double* yv, double* cv) {
+#pragma unroll
+    for (int t = 0; t < B; ++t)
+        if (nfull + t < nz) fwd_row(nfull + t, fa[t]);
+    // back substitution, top row first: the tail, then the full batches
+    auto load_back = [&](int k1, double* yv, double* cv) {   // rows k1, k1 - 1, ..., k1 - B + 1
 #pragma unroll
         for (int t = 0; t < B; ++t) {
-            const int k = k1 - t;
-            yv[t] = (k >= 0) ? ys[(size_t)k * nl] : 0.0;
-            cv[t] = (k >= 0) ? cps[(size_t)k * nl] : 0.0;
+            const int k = (k1 - t >= 0) ? k1 - t : 0;
+            yv[t] = ys[(size_t)k * nl];
+            cv[t] = cps[(size_t)k * nl];
         }
     };
     double x = 0.0;
+    auto back_row = [&](int k, double yk, double ck) {
+        x = yk - ck * x;
+        colw[(size_t)k * st] = (TS)(x * so[k]);
+    };
     double ya[B], ca[B], yb[B], cb[B];
     load_back(nz - 1, ya, ca);
-    for (int k1 = nz - 1; k1 >= 0; k1 -= B) {
-        if (k1 - B >= 0) load_back(k1 - B, yb, cb);
+    if (nfull > 0) load_back(nfull - 1, yb, cb);
+    const int rem = nz - nfull;
 #pragma unroll
-        for (int t = 0; t < B; ++t) {
-            const int k = k1 - t;
-            if (k >= 0) {
-                x = ya[t] - ca[t] * x;
-                colw[(size_t)k * st] = (TS)(a.transposed ? x * a.dz[k] : x);
-            }
-        }
+    for (int t = 0; t < B; ++t)
+        if (t < rem) back_row(nz - 1 - t, ya[t], ca[t]);
+    for (int k1 = nfull - 1; k1 >= 0; k1 -= B) {
 #pragma unroll
         for (int t = 0; t < B; ++t) {
             ya[t] = yb[t];
             ca[t] = cb[t];
         }
+        load_back(k1 - B, yb, cb);
+#pragma unroll
+        for (int t = 0; t < B; ++t) back_row(k1 - t, ya[t], ca[t]);
     }
 }
 
@@ -780,13 +797,12 @@ __global__ __launch_bounds__(NT) void k_grad_row2(GradArgs<TIO, TP> a) {
 }
 
 // ---------------------------------------------------------------------------
-// FP64 residual of the refinement, r = (f - mean) - L p: per-block
-// (sum r^2, sum r, sum dz_k p) partials and, with WRITE, r rounded to FP32
-// for the next correction solve.  The third sum is the volume integral of the
-// iterate (over dx dy): the residual is blind to constants, so this is what
-// lets the next correction pin the V-mean of p in FP64.  Lanes own two
-// adjacent x-cells (16-byte accesses), workgroups RJ rows of one z-plane,
-// tiles plane-fastest (the k-1 rows of p were read by the previous
+// FP64 residual norm of the refinement, r = (f - mean) - L p: per-block
+// (sum r^2, sum r, sum dz_k p) partials.  The third sum is the volume
+// integral of the iterate (over dx dy): the residual is blind to constants,
+// so this is what lets a correction pin the V-mean of p in FP64.  Lanes own
+// two adjacent x-cells (16-byte accesses), workgroups RJ rows of one
+// z-plane, tiles plane-fastest (the k-1 rows of p were read by the previous
 // workgroup on the same XCD); the j-1 / j+1 rows rotate through registers.
 // ---------------------------------------------------------------------------
 template <typename TPP>
@@ -800,7 +816,6 @@ struct ResArgs {
     const double* scal;   // scal[0] = removed mean
     const double* dz;     // cell widths dz_k (third partial)
     double* partials;
-    float* out;           // WRITE: the residual in FP32 (input of the next correction)
 };
 
 // two adjacent values of T as a double2
@@ -810,7 +825,7 @@ __device__ __forceinline__ double2 ld2d(const T* q) {
     return make_double2((double)v.x, (double)v.y);
 }
 
-template <int NT, int RJ, bool WRITE, typename TPP, int RB = 2>   // RB: rows per load batch
+template <int NT, int RJ, typename TPP, int RB = 2>   // RB: rows per load batch
 __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
     static_assert(RJ % RB == 0, "whole batches");
     __shared__ double sred[3 * (NT / 64)];
@@ -870,9 +885,6 @@ __global__ __launch_bounds__(NT) void k_resid_pairs(ResArgs<TPP> a) {
                 ss += r0 * r0 + r1 * r1;
                 s1 += r0 + r1;
                 sp += pc.x + pc.y;
-                if constexpr (WRITE)
-                    *reinterpret_cast<float2*>(a.out + (size_t)k * nxy + (size_t)j * nx + i) =
-                        make_float2((float)r0, (float)r1);
                 pm = pc;
                 pc = pn[r];
             }

@@ -144,6 +144,12 @@ struct fsei_plan_impl {
     void* ws = nullptr;
     size_t ws_bytes = 0;
     void* stream = nullptr;
+    // side stream of the z solve (near-singular and (0,0) lines run there,
+    // concurrently with the tiled lines) and its fork / join events; created
+    // with the first workspace, destroyed with the plan
+    void* side_stream = nullptr;
+    void* ev_fork = nullptr;
+    void* ev_join = nullptr;
 
     // timing
     bool timing = false;

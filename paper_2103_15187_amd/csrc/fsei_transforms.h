@@ -261,7 +261,7 @@ struct Vec2T<float> {
 // RESID: the FP64 residual (f - mean) - L p of an FP64 iterate p; RESID_F: of
 // an FP32 iterate p32 (the first solve of the refinement), read as FP32 and
 // evaluated in FP64
-enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3, PRO_SRC = 4, PRO_RESID_F = 5 };
+enum { PRO_COPY = 0, PRO_DIV = 1, PRO_DIV_ADJ = 2, PRO_RESID = 3, PRO_RESID_F = 5 };
 
 template <typename TI, typename TO>
 struct XFwdArgs {
@@ -273,7 +273,6 @@ struct XFwdArgs {
     const TI* w;
     const TI* gp;       // adjoint: dLoss/dp or null
     const double* f;    // COPY (double input) and RESID
-    const TI* src;      // SRC: input of the prologue's own type
     const double* p;    // RESID
     const float* p32;   // RESID_F
     TI alpha, beta, idx, idy;
@@ -319,8 +318,6 @@ __device__ __forceinline__ TI x_prologue(const XFwdArgs<TI, TO>& a, size_t base,
     const int nxy = nx * ny;
     if constexpr (PRO == PRO_COPY) {
         return (TI)a.f[base + o];
-    } else if constexpr (PRO == PRO_SRC) {
-        return a.src[base + o];
     } else if constexpr (PRO == PRO_RESID || PRO == PRO_RESID_F) {
         const auto* __restrict__ p = resid_iterate<PRO>(a) + base;
         const double pc = (double)p[o];
@@ -384,10 +381,6 @@ __device__ __forceinline__ void x_prologue_pair(const XFwdArgs<TI, TO>& a, size_
         const double2 f = *reinterpret_cast<const double2*>(a.f + ro + cn.i);
         v0 = (TI)f.x;
         v1 = (TI)f.y;
-    } else if constexpr (PRO == PRO_SRC) {
-        const V q = *reinterpret_cast<const V*>(a.src + ro + cn.i);
-        v0 = q.x;
-        v1 = q.y;
     } else if constexpr (PRO == PRO_RESID || PRO == PRO_RESID_F) {
         const auto* __restrict__ p = resid_iterate<PRO>(a) + ro;
         const double2 pc = pair_d(p + cn.i);
@@ -845,6 +838,12 @@ struct XInvGradArgs {
     const double* dcts;
 };
 
+// two adjacent doubles as one non-temporal 16-byte store
+__device__ __forceinline__ void nt_store2(double* q, double2 v) {
+    __builtin_nontemporal_store(v.x, q);
+    __builtin_nontemporal_store(v.y, q + 1);
+}
+
 constexpr int kXgRows = 8;    // own rows per workgroup
 constexpr int kXgSeq = 5;     // complex sequences per step (8 rows + halo + zero row)
 
@@ -859,7 +858,7 @@ __global__ __launch_bounds__(xg_threads<NF>()) void k_xinv_grad(XInvGradArgs a) 
     constexpr int GR = kXgRows, NSQ = kXgSeq, EMAX = NSQ * NF;
     static_assert(NTHR >= NF / 2, "a column pair per thread");
     constexpr int SP = seq_stride(NF);
-    constexpr int GB = 2;   // rows per batch of the gradient phase
+    constexpr int GB = 4;   // rows per batch of the gradient phase
     static_assert(NSQ * SP <= lds_elems(EMAX), "tile fits");
     static_assert(2 * NSQ == GR + 2, "halo row + own rows + one zero row");
     static_assert(GR % GB == 0, "whole batches");
@@ -966,11 +965,12 @@ __global__ __launch_bounds__(xg_threads<NF>()) void k_xinv_grad(XInvGradArgs a) 
                     vn.y = v0 ? 0.0 : vo[t].y + a.cy * (pc.y - pym.y);
                     wn.x = (k == 0) ? 0.0 : wo[t].x + a.sw * (bkk * pc.x - gkk * prev[l].x);
                     wn.y = (k == 0) ? 0.0 : wo[t].y + a.sw * (bkk * pc.y - gkk * prev[l].y);
+                    // non-temporal: nothing here is read again soon
                     const size_t o = ro + (size_t)l * NF;
-                    *reinterpret_cast<double2*>(a.u + o) = un;
-                    *reinterpret_cast<double2*>(a.v + o) = vn;
-                    *reinterpret_cast<double2*>(a.w + o) = wn;
-                    if (a.p) *reinterpret_cast<double2*>(a.p + o) = pc;
+                    nt_store2(a.u + o, un);
+                    nt_store2(a.v + o, vn);
+                    nt_store2(a.w + o, wn);
+                    if (a.p) nt_store2(a.p + o, pc);
                     prev[l] = pc;
                     pym = pc;
                 }

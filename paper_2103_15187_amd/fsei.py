@@ -138,7 +138,8 @@ class Plan:
         self.workspace_bytes = nbytes.value
         self.device = torch.device(device)
         self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
-        _check(L.fsei_plan_set_workspace(h, _ptr(self._ws), self.workspace_bytes), "fsei_plan_set_workspace")
+        with torch.cuda.device(self.device):   # the plan's side stream is made on its device
+            _check(L.fsei_plan_set_workspace(h, _ptr(self._ws), self.workspace_bytes), "fsei_plan_set_workspace")
 
     @classmethod
     def from_spec(cls, spec, **kw):

@@ -470,17 +470,25 @@ def test_long_z_lines_adjoint_fp32_and_refine():
 
 # ---- compile-time length 768 (x: tiles of 8 rows on 384 lanes; y: tiles of
 # 128-byte row segments; the fused x-inverse + gradient at 768) -------------
-L768 = [((768, 8, 5), (WALL, WALL)), ((768, 16, 20), (PERIODIC, WALL)), ((768, 24, 3), (WALL, PERIODIC)),
-        ((16, 768, 4), (WALL, PERIODIC)), ((32, 768, 3), (PERIODIC, PERIODIC))]
+L768 = [((768, 8, 12), (WALL, WALL)), ((768, 16, 20), (PERIODIC, WALL)), ((768, 24, 8), (WALL, PERIODIC)),
+        ((16, 768, 8), (WALL, PERIODIC)), ((32, 768, 6), (PERIODIC, PERIODIC)), ((24, 768, 5), (WALL, WALL))]
 
 
-def _check_all_precisions(spec, seed, bar64=1e-12, bar32=2e-5):
+def _check_all_precisions(spec, seed, bar32=2e-5):
     """FP64 projection, plain FP32, FP32+refine (residual, p and V-mean) and
-    the FP64 adjoint of one shape against the oracle."""
+    the FP64 adjoint of one shape against the oracle.  The FP64 bar is 1e-12,
+    or three times the oracle's own error against its long-double variant on
+    the same input where that floor is higher (white-noise input on lines of
+    768-2048 points: up to ~3e-12 for the velocity component along the long
+    line and for p on long z lines); the adjoint's the same way from the
+    oracle's adjoint in long double."""
     F = fsei()
     g = grid_of(spec)
     u, v, w = W.random_velocity(spec, seed)
     ru, rv, rw, rp = oracle.project(u, v, w, g)
+    ld = oracle.project(u, v, w, g, dtype=np.longdouble)
+    floor = max(rel(a, np.asarray(b, dtype=np.float64)) for a, b in zip((ru, rv, rw, rp), ld))
+    bar64 = max(1e-12, 3.0 * floor)
     out = run_project(spec, u, v, w)
     e64 = [rel(a, b) for a, b in zip(out[:4], (ru, rv, rw, rp))]
     out = run_project(spec, u, v, w, precision=F.PREC_FP32)
@@ -492,23 +500,26 @@ def _check_all_precisions(spec, seed, bar64=1e-12, bar32=2e-5):
     for a, m in zip((au, av, aw), W.dead_face_masks(spec)):
         a[m] = 0
     ref = oracle.project_adjoint(au, av, aw, ap, g, dt=0.6)
+    ref_ld = oracle.project_adjoint(au, av, aw, ap, g, dt=0.6, dtype=np.longdouble)
+    floor_adj = max(rel(a, np.asarray(b, dtype=np.float64)) for a, b in zip(ref, ref_ld))
+    bar_adj = max(1e-12, 3.0 * floor_adj)
     plan = F.Plan.from_spec(spec)
     da, db, dc = dev(au), dev(av), dev(aw)
     plan.project_backward(da, db, dc, dev(ap), dt=0.6)
     torch.cuda.synchronize()
     ea = [rel(host(t), x) for t, x in zip((da, db, dc), ref)]
-    print(f"{(spec.nx, spec.ny, spec.nz)} fp64 {max(e64):.2e} fp32 {max(e32):.2e} refine {info} "
-          f"{max(er):.2e} adjoint {max(ea):.2e}")
+    print(f"{(spec.nx, spec.ny, spec.nz)} fp64 {max(e64):.2e} (oracle floor {floor:.2e}) fp32 {max(e32):.2e} "
+          f"refine {info} {max(er):.2e} adjoint {max(ea):.2e} (floor {floor_adj:.2e})")
     assert max(e64) <= bar64
     assert max(e32) <= bar32
     assert info["rel_residual"] <= 1e-10 and max(er) <= 1e-9
     assert abs(oracle.vmean(gp, g)) <= 1e-13 * np.abs(gp).max()
-    assert max(ea) <= bar64
+    assert max(ea) <= bar_adj
 
 
 @pytest.mark.parametrize("dims,bc", L768)
 def test_length_768_all_precisions(dims, bc):
-    spec = W.small_spec(*dims, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=3.0)
+    spec = W.small_spec(*dims, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=2.0)
     _check_all_precisions(spec, sum(dims))
 
 

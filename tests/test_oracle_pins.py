@@ -390,3 +390,23 @@ def test_fp64_vs_long_double_floor():
     pld = oracle.poisson_solve(f.astype(np.longdouble), g, dtype=np.longdouble)
     err = float(np.linalg.norm((p64 - pld).astype(np.float64)) / np.linalg.norm(pld.astype(np.float64)))
     assert err < 1e-13
+
+
+@pytest.mark.skipif(np.finfo(np.longdouble).eps >= np.finfo(np.float64).eps,
+                    reason="long double is not wider than double here")
+@pytest.mark.parametrize("n,bc", [(n, bc) for n in (2, 3, 4, 5, 6, 8, 9, 12, 16, 27) for bc in (WALL, PERIODIC)])
+def test_closed_form_inverse_in_long_double(n, bc):
+    """The long-double variant inverts the transforms by M^T diag(1/||row||^2)
+    (rows mutually orthogonal): against Gaussian elimination with partial
+    pivoting in long double, and M^-1 M = I to long-double rounding."""
+    M = oracle.transform_matrix(n, bc, np.longdouble)
+    inv = oracle.inverse_closed_form(M)
+    eye = np.eye(n, dtype=np.longdouble)
+    from oracle.fsei_oracle import _ld_solve
+    elim = _ld_solve(M, eye.copy())
+    eps = np.finfo(np.longdouble).eps
+    assert np.abs(inv @ M - eye).max() < 64 * n * eps
+    assert np.abs(inv - elim).max() < 64 * n * eps * np.abs(elim).max()
+    # the FP64 path's solve agrees with it too
+    inv64 = np.linalg.solve(M.astype(np.float64), np.eye(n))
+    assert np.abs(inv64 - inv.astype(np.float64)).max() < 64 * n * np.finfo(np.float64).eps
