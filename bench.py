@@ -563,6 +563,69 @@ def err_vs_oracle(spec, oracle_out, torch, fsei):
     return out
 
 
+def transform_ab(torch, fsei):
+    """The y transform of the 768 x 768 x 1024 grid two ways: this library's
+    LDS FFT kernels (forward + inverse, from the per-kernel times of FP64 and
+    FP32 projections) and transform-as-GEMM on the matrix cores through the
+    platform GEMM library (torch.matmul): (a) dense, Y_k = M (768 x 768) X_k
+    per z-plane; (b) four-step, 768 = 24 x 32 on complex sequences (two real
+    lines each): 32-point DFTs as a GEMM, the twiddle multiply, 24-point DFTs
+    as a GEMM, transposes not counted.  Median of 5 event-timed runs."""
+    from paper_2103_15187_amd import workloads as W
+    spec = W.CONFIGS["C5"]
+    nx, ny, nz = spec.nx, spec.ny, spec.nz
+
+    def timeit(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+    out = {"workload": f"y transform of {nx}x{ny}x{nz} (lines of {ny} points), forward",
+           "lds_fft_ms": {}, "gemm_dense_ms": {}, "gemm_four_step_ms": {}}
+    for name, prec, dt in (("fp64", fsei.PREC_FP64, torch.float64), ("fp32", fsei.PREC_FP32, torch.float32)):
+        plan = fsei.Plan.from_spec(spec, precision=prec)
+        u, v, w = (torch.randn(spec.shape, dtype=dt, device="cuda") for _ in range(3))
+        for a, m in zip((u, v, w), W.dead_face_masks(spec)):
+            a[torch.from_numpy(m).cuda()] = 0
+        plan.project(u, v, w, want_p=False)
+        torch.cuda.synchronize()
+        plan.reset_timing()
+        plan.set_timing(True)
+        for _ in range(3):
+            plan.project(u, v, w, want_p=False)
+        torch.cuda.synchronize()
+        plan.set_timing(False)
+        kt = plan.kernel_times()
+        out["lds_fft_ms"][name] = round(kt["yfwd"][0] / kt["yfwd"][1], 4)
+        del plan, u, v, w
+        torch.cuda.empty_cache()
+        X = torch.randn(nz, ny, nx, dtype=dt, device="cuda")
+        M = torch.randn(ny, ny, dtype=dt, device="cuda")
+        Y = torch.empty_like(X)
+        out["gemm_dense_ms"][name] = round(timeit(lambda: torch.matmul(M, X, out=Y)), 4)
+        del X, Y
+        torch.cuda.empty_cache()
+        ct = torch.complex128 if dt == torch.float64 else torch.complex64
+        Z = torch.randn(nz * nx // 2, 24, 32, dtype=ct, device="cuda")
+        F32, F24, T = (torch.randn(s, dtype=ct, device="cuda") for s in ((32, 32), (24, 24), (24, 32)))
+
+        def four_step():
+            A = torch.matmul(Z, F32)
+            A.mul_(T)
+            return torch.matmul(F24, A)
+        out["gemm_four_step_ms"][name] = round(timeit(four_step), 4)
+        del Z
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -580,6 +643,9 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also run torch.neg over one field (a plain streaming kernel of known size: "
                          "reads and writes 8 B per cell) to calibrate hardware byte counters")
+    ap.add_argument("--transform-ab", action="store_true",
+                    help="time the 768-point y transform as this library's LDS FFT and as transform-as-GEMM on "
+                         "the matrix cores (dense and four-step), print that as the one JSON line and exit")
     ap.add_argument("--summarize", metavar="DIR",
                     help="write profiles/ summaries from the rocprofv3 outputs under DIR and exit")
     args = ap.parse_args()
@@ -603,6 +669,9 @@ def main():
         sys.exit(2)
     import torch
     from paper_2103_15187_amd import fsei, workloads as W
+    if args.transform_ab:
+        print(json.dumps({"transform_ab": transform_ab(torch, fsei)}), flush=True)
+        return
     spec = W.CONFIGS[args.config]
     log(f"[bench] generating {args.config} input {spec.shape}")
     if args.config == "C3":

@@ -2,7 +2,9 @@
 faces are ignored on input and written 0 on output, in the projection and
 in its adjoint, for every precision mode and for the fixed-length and generic
 kernel paths; the adjoint and the autograd wrapper under FP32_REFINE plans
-(the adjoint is computed in FP64 there)."""
+(the adjoint is computed in FP64 there).  FP64 bars: 1e-12, or three times
+the oracle's own error against its long-double variant where that is higher
+(768-point lines); plain FP32 5e-5 (as for the other 768-point tests)."""
 import numpy as np
 import pytest
 
@@ -54,6 +56,10 @@ def test_projection_ignores_and_zeroes_dead_faces(dims, bc, prec):
     g = grid_of(spec)
     clean = W.random_velocity(spec, 61)
     ref = oracle.project(*clean, g, dt=0.9)
+    # FP64 bar: 1e-12, or 3x the oracle's own error against long double where
+    # that floor is higher (lines of 768 points)
+    ld = oracle.project(*clean, g, dt=0.9, dtype=np.longdouble)
+    bar64 = max(1e-12, 3.0 * max(rel(a, np.asarray(b, dtype=np.float64)) for a, b in zip(ref, ld)))
     dirty = with_garbage(clean, spec, 62)
     kw = {"fp64": {}, "fp32": dict(precision=F.PREC_FP32),
           "fp32_refine": dict(precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6)}[prec]
@@ -65,7 +71,7 @@ def test_projection_ignores_and_zeroes_dead_faces(dims, bc, prec):
     out = [t.double().cpu().numpy() for t in (*d, p)]
     errs = [rel(a, b) for a, b in zip(out, ref)]
     print(dims, bc, prec, errs)
-    assert max(errs) <= {"fp64": 1e-12, "fp32": 2e-5, "fp32_refine": 1e-9}[prec]
+    assert max(errs) <= {"fp64": bar64, "fp32": 5e-5, "fp32_refine": 1e-9}[prec]
     for a, m in zip(out[:3], W.dead_face_masks(spec)):
         assert np.all(a[m] == 0.0)
 
@@ -82,6 +88,8 @@ def test_adjoint_ignores_and_zeroes_dead_faces(dims, bc, prec):
     r = W.rng(63)
     gu, gv, gw, gp = (r.standard_normal(spec.shape) for _ in range(4))
     ref = oracle.project_adjoint(gu, gv, gw, gp, g, dt=0.7)
+    ld = oracle.project_adjoint(gu, gv, gw, gp, g, dt=0.7, dtype=np.longdouble)
+    bar = max(1e-12, 3.0 * max(rel(a, np.asarray(b, dtype=np.float64)) for a, b in zip(ref, ld)))
     kw = {} if prec == "fp64" else dict(precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=4)
     plan = F.Plan.from_spec(spec, **kw)
     d = [dev(a) for a in with_garbage((gu, gv, gw), spec, 64)]
@@ -90,7 +98,7 @@ def test_adjoint_ignores_and_zeroes_dead_faces(dims, bc, prec):
     out = [t.cpu().numpy() for t in d]
     errs = [rel(a, b) for a, b in zip(out, ref)]
     print(dims, bc, prec, errs)
-    assert max(errs) <= 1e-12
+    assert max(errs) <= bar
     for a, m in zip(out, W.dead_face_masks(spec)):
         assert np.all(a[m] == 0.0)
 
