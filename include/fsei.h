@@ -64,7 +64,9 @@ typedef enum {
     FSEI_ERR_NOT_CONVERGED = -6, /* FP32_REFINE did not reach rtol (max_iter corrections done, or the
                                     residual stopped decreasing: fsei_info.floor_reached); outputs hold
                                     the last iterate */
-    FSEI_ERR_PRECISION = -7      /* entry point does not match the plan's precision mode */
+    FSEI_ERR_PRECISION = -7,     /* entry point does not match the plan's precision mode */
+    FSEI_ERR_SCRATCH = -8        /* fsei_project_noalloc: the plan's workspace size exceeds the
+                                    library's static scratch (fsei_project_noalloc_max_bytes) */
 } fsei_status;
 
 /* Boundary condition of the x and y directions (z always has walls). */
@@ -137,6 +139,27 @@ fsei_status fsei_poisson_solve(fsei_plan* plan, const double* f, double* p, fsei
  *   info    : optional (host); when given the call waits for the stream. */
 fsei_status fsei_project(fsei_plan* plan, double* u, double* v, double* w, double* p, double dt,
                          fsei_info* info);
+
+/* Allocation-free projection, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same operation, arguments, precision modes and results
+ * as fsei_project (the same kernels), but the workspace is the library's own
+ * static device array of fsei_project_noalloc_max_bytes() bytes (128 MiB),
+ * one per GPU, held until the process ends; no workspace needs to be set on
+ * the plan and none is used.  The call allocates nothing (no hipMalloc, no
+ * library allocation); it copies the plan's tables into the array (host to
+ * device, on the plan's stream) and clears its scalars with a kernel.
+ *   Limit: fsei_plan_workspace_size(plan) must not exceed
+ *   fsei_project_noalloc_max_bytes(), else FSEI_ERR_SCRATCH before any work
+ *   (FP64: about 16 M cells; FP32_REFINE: about 5 M cells).
+ *   Sharing: all calls on one GPU use the same array, which keeps the last
+ *   call's contents; calls that overlap on one GPU (two streams, two threads)
+ *   race and give wrong results.  Serialise them. */
+fsei_status fsei_project_noalloc(fsei_plan* plan, double* u, double* v, double* w, double* p, double dt,
+                                 fsei_info* info);
+
+/* Size in bytes of the static scratch of fsei_project_noalloc. */
+size_t fsei_project_noalloc_max_bytes(void);
 
 /* Adjoint of fsei_project with respect to u* (double I/O; FP64 or
  * FP32_REFINE plans, computed in FP64):

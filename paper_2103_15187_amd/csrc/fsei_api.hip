@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1155,6 +1156,38 @@ fsei_status project_impl(fsei_plan* p, double* u, double* v, double* w, double* 
     return FSEI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Device-resident scratch of the allocation-free projection: one copy per
+// GPU, held until the process ends.  Host code never uses the array's name
+// as an address: the device address comes from hipGetSymbolAddress, once per
+// device, and is kept in scratch_ptr.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+__global__ __launch_bounds__(256) void k_zero(double* __restrict__ q, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) q[i] = 0.0;
+}
+
+fsei_status scratch_of_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return FSEI_ERR_HIP;
+    if (dev >= kMaxDevices) return FSEI_ERR_HIP;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_ptr[dev] == nullptr) {
+        void* q = nullptr;
+        if (hipGetSymbolAddress(&q, HIP_SYMBOL(scratch)) != hipSuccess || q == nullptr) return FSEI_ERR_HIP;
+        scratch_ptr[dev] = q;
+    }
+    *out = scratch_ptr[dev];
+    return FSEI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1166,6 +1199,45 @@ fsei_status fsei_project(fsei_plan* p, double* u, double* v, double* w, double* 
     if (!good_dt(dt)) return FSEI_ERR_ARG;
     if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
     return project_impl(p, u, v, w, pout, dt, info);
+}
+
+size_t fsei_project_noalloc_max_bytes(void) { return kScratchBytes; }
+
+fsei_status fsei_project_noalloc(fsei_plan* p, double* u, double* v, double* w, double* pout, double dt,
+                                 fsei_info* info) {
+    if (!p || !u || !v || !w) return FSEI_ERR_ARG;
+    if (!good_dt(dt)) return FSEI_ERR_ARG;
+    if (p->precision == FSEI_PREC_FP32) return FSEI_ERR_PRECISION;
+    if (p->ws_total > kScratchBytes) return FSEI_ERR_SCRATCH;
+    void* sp = nullptr;
+    fsei_status st = scratch_of_current_device(&sp);
+    if (st != FSEI_OK) return st;
+    // this plan's tables (and FP64 line list) into the shared scratch, the
+    // scalars cleared by a kernel; everything on the plan's stream, so the
+    // copies are ordered before the kernels that read them
+    hipStream_t s = S(p);
+    if (hipMemcpyAsync((char*)sp + p->ws_tab_d, p->tab_d.data(), p->tab_d.size() * sizeof(double),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return FSEI_ERR_HIP;
+    if (hipMemcpyAsync((char*)sp + p->ws_tab_f, p->tab_f.data(), p->tab_f.size() * sizeof(float),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return FSEI_ERR_HIP;
+    if (!p->list_host.empty() &&
+        hipMemcpyAsync((char*)sp + p->ws_list, p->list_host.data(), p->list_host.size() * sizeof(int),
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return FSEI_ERR_HIP;
+    constexpr int nsc = fsei_plan_impl::kScalars;
+    hipLaunchKernelGGL(k_zero, dim3((nsc + 255) / 256), dim3(256), 0, s,
+                       reinterpret_cast<double*>((char*)sp + p->ws_scalars), nsc);
+    void* ws0 = p->ws;
+    const size_t bytes0 = p->ws_bytes;
+    p->ws = sp;
+    p->ws_bytes = kScratchBytes;
+    st = check_hip();
+    if (st == FSEI_OK) st = project_impl(p, u, v, w, pout, dt, info);
+    p->ws = ws0;
+    p->ws_bytes = bytes0;
+    return st;
 }
 
 fsei_status fsei_project_backward(fsei_plan* p, double* gu, double* gv, double* gw, const double* gp, double dt) {

@@ -213,6 +213,7 @@ const char* fsei_status_string(fsei_status s) {
         case FSEI_ERR_HIP: return "FSEI_ERR_HIP: HIP runtime error";
         case FSEI_ERR_NOT_CONVERGED: return "FSEI_ERR_NOT_CONVERGED: refinement did not reach rtol";
         case FSEI_ERR_PRECISION: return "FSEI_ERR_PRECISION: entry point does not match the plan precision";
+        case FSEI_ERR_SCRATCH: return "FSEI_ERR_SCRATCH: the plan's workspace exceeds the allocation-free scratch";
     }
     return "unknown fsei_status";
 }

@@ -68,6 +68,8 @@ def lib():
         "fsei_plan_set_stream": (I, [P, P]),
         "fsei_poisson_solve": (I, [P, P, P, ctypes.POINTER(Info)]),
         "fsei_project": (I, [P, P, P, P, P, D, ctypes.POINTER(Info)]),
+        "fsei_project_noalloc": (I, [P, P, P, P, P, D, ctypes.POINTER(Info)]),
+        "fsei_project_noalloc_max_bytes": (S, []),
         "fsei_project_backward": (I, [P, P, P, P, P, D]),
         "fsei_project_f32": (I, [P, P, P, P, P, ctypes.c_float]),
         "fsei_project_backward_f32": (I, [P, P, P, P, P, ctypes.c_float]),
@@ -112,7 +114,7 @@ class Plan:
     The workspace is a torch uint8 tensor on `device`."""
 
     def __init__(self, nx, ny, nz, bc, dx, dy, zc, precision=PREC_FP64, rtol=1e-10, max_iter=4,
-                 device="cuda", accept_floor=False):
+                 device="cuda", accept_floor=False, workspace=True):
         import torch
         L = lib()
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
@@ -137,9 +139,12 @@ class Plan:
         _check(L.fsei_plan_workspace_size(h, ctypes.byref(nbytes)), "fsei_plan_workspace_size")
         self.workspace_bytes = nbytes.value
         self.device = torch.device(device)
-        self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
-        with torch.cuda.device(self.device):   # the plan's side stream is made on its device
-            _check(L.fsei_plan_set_workspace(h, _ptr(self._ws), self.workspace_bytes), "fsei_plan_set_workspace")
+        self._ws = None
+        if workspace:
+            # workspace=False: a plan for project_noalloc only (no device memory)
+            self._ws = torch.empty(max(self.workspace_bytes, 256), dtype=torch.uint8, device=self.device)
+            with torch.cuda.device(self.device):   # the plan's side stream is made on its device
+                _check(L.fsei_plan_set_workspace(h, _ptr(self._ws), self.workspace_bytes), "fsei_plan_set_workspace")
 
     @classmethod
     def from_spec(cls, spec, **kw):
@@ -216,6 +221,22 @@ class Plan:
         want = info or self._floor_ok()
         self._status(lib().fsei_project(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(p), float(dt),
                                         ctypes.byref(inf) if want else None), "fsei_project", inf)
+        return (p, _info_dict(inf)) if info else p
+
+    def project_noalloc(self, u, v, w, p=None, dt=1.0, info=False):
+        """As project (double I/O plans), on the library's static device
+        scratch instead of the plan's workspace; allocates nothing itself
+        (p must then be given, or no pressure is returned)."""
+        import torch
+        u, v, w = (self._field(a, torch.float64, n) for a, n in ((u, "u"), (v, "v"), (w, "w")))
+        p = self._field(p, torch.float64, "p")
+        self._stream()
+        inf = Info()
+        want = info or self._floor_ok()
+        with torch.cuda.device(self.device):   # the scratch copy of the plan's GPU
+            st = lib().fsei_project_noalloc(self._h, _ptr(u), _ptr(v), _ptr(w), _ptr(p), float(dt),
+                                            ctypes.byref(inf) if want else None)
+        self._status(st, "fsei_project_noalloc", inf)
         return (p, _info_dict(inf)) if info else p
 
     def project_backward(self, gu, gv, gw, gp=None, dt=1.0):
