@@ -337,8 +337,8 @@ def summarize_profiles(d, cmd_trace, cmd_pmc):
     import csv
     out = os.path.join(ROOT, "profiles")
     rows = list(csv.DictReader(open(os.path.join(d, "prof", "c3_kernel_stats.csv"))))
-    md = ["# Kernel trace: projection (FP32+refine and FP64 modes) and implicit viscous step, "
-          "512x512x768 walls tanh 2.5", "",
+    md = ["# Kernel trace: projection (FP32+refine and FP64 modes), viscous step, momentum right-hand side "
+          "and IB-MLS transfer, 512x512x768 walls tanh 2.5", "",
           "Command (run from the repository root on one MI355X):", "", "```", cmd_trace, "```", "",
           "| kernel | calls | avg (us) | total (ms) | % |", "|---|---:|---:|---:|---:|"]
     for r in rows:
@@ -386,6 +386,45 @@ def summarize_profiles(d, cmd_trace, cmd_pmc):
                   f"{e.get('write_bytes', 0) / spec_cells:.2f} | "
                   f"{(e.get('fetch_bytes', 0) + e.get('write_bytes', 0)) / 1e9:.3f} |")
     with open(os.path.join(out, "hbm_traffic_c3_512x512x768.md"), "w") as fh:
+        fh.write("\n".join(md) + "\n")
+    ab_csv = os.path.join(d, "prof_ab", "ab_kernel_stats.csv")
+    if os.path.exists(ab_csv):
+        summarize_transform_ab(d, ab_csv, out)
+
+
+def summarize_transform_ab(d, ab_csv, out):
+    """profiles/transform_ab_768x768x1024.md from the kernel trace of
+    `bench.py --transform-ab` and the JSON line it printed."""
+    import csv
+    rows = list(csv.DictReader(open(ab_csv)))
+    res = None
+    log_path = os.path.join(d, "prof_ab.log")
+    if os.path.exists(log_path):
+        for ln in open(log_path):
+            if ln.startswith("{") and "transform_ab" in ln:
+                res = json.loads(ln)["transform_ab"]
+    md = ["# Transform A/B: the 768-point y transform as LDS FFT kernels and as transform-as-GEMM on the "
+          "matrix cores, 768x768x1024", "",
+          "Command (run from the repository root on one MI355X):", "", "```",
+          "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_ab -o ab --output-format csv -- "
+          "python3 bench.py --transform-ab", "python3 bench.py --summarize gpurun_out", "```", ""]
+    if res:
+        md += ["Event-timed medians printed by the run (ms per forward y transform of the whole grid):", "",
+               "| variant | FP32 | FP64 |", "|---|---:|---:|"]
+        for key, name in (("lds_fft_ms", "LDS FFT (`k_yfwd`, this library)"),
+                          ("gemm_dense_ms", "dense GEMM, M (768x768) X_k per plane"),
+                          ("gemm_four_step_ms", "four-step 24x32 GEMMs + twiddles (transposes not counted)")):
+            md.append(f"| {name} | {res[key].get('fp32', float('nan')):.3f} | {res[key].get('fp64', float('nan')):.3f} |")
+        md.append("")
+    md += ["Kernel trace (all kernels of the run; the projections that time the LDS kernels also run their other "
+           "kernels):", "", "| kernel | calls | avg (us) | total (ms) |", "|---|---:|---:|---:|"]
+    for r in rows:
+        name = _short_kernel(r["Name"])
+        if len(name) > 80:
+            name = name[:80] + "..."
+        md.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                  f"{float(r['TotalDurationNs']) / 1e6:.2f} |")
+    with open(os.path.join(out, "transform_ab_768x768x1024.md"), "w") as fh:
         fh.write("\n".join(md) + "\n")
 
 
