@@ -262,6 +262,11 @@ void launch_xinv_grad(fsei_plan* p, const double* in, double* pout, double* u, d
         hipLaunchKernelGGL((k_xinv_grad<512>), grid, dim3(xg_threads<512>()), 2 * 512 * sizeof(double), S(p), a);
 }
 
+// dynamic LDS of the compile-time-length y forward kernel: the FFT twiddles,
+// and for FP32 also the DCT post-twiddles
+template <typename T>
+size_t yfwd_dyn(int nf) { return (sizeof(T) == 4 ? 4 : 2) * (size_t)nf * sizeof(T); }
+
 template <typename T, int EMAX, int NTHR>
 void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     a.nseq = std::max(1, std::min(tile_nseq(EMAX, p->ny), (p->nx + 1) / 2));
@@ -276,8 +281,11 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
     // fixed-length variant: full tiles of the compile-time width, column
     // pairs addressed as one aligned vector
     constexpr int kPsF = yfwd_pad<T>();
+    // (an FP64 512 line always takes the 4096-element tile: the wider FP64
+    // configuration is not compiled for it)
     constexpr bool kFix = y_fixed_ok(EMAX, NTHR, 512) && y_fixed_ok(EMAX, NTHR, 512, kPsF) &&
-                          tile_nseq(EMAX, 512, kPsF) == tile_nseq(EMAX, 512);
+                          tile_nseq(EMAX, 512, kPsF) == tile_nseq(EMAX, 512) &&
+                          (sizeof(T) == 4 || EMAX <= 4096);
     const bool fix = kFix && p->ny == 512 && a.nseq == tile_nseq(EMAX, 512) && p->nx % tx == 0 &&
                      reinterpret_cast<uintptr_t>(a.data) % (2 * sizeof(T)) == 0;
     if (inverse) {
@@ -293,7 +301,8 @@ void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
         Timed t(p, K_YFWD);
         if constexpr (kFix) {
             if (fix) {
-                hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512, kPsF>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+                hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, 512, kPsF>), dim3(nb), dim3(NTHR), yfwd_dyn<T>(512), S(p),
+                                   a);
                 return;
             }
         }
@@ -327,7 +336,7 @@ bool launch_y768(fsei_plan* p, YArgs<T> a, bool inverse) {
         hipLaunchKernelGGL((k_yinv<T, EMAX, NTHR, NF>), dim3(nb), dim3(NTHR), dyn, S(p), a);
     } else {
         Timed t(p, K_YFWD);
-        hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, NF, kPsF>), dim3(nb), dim3(NTHR), dyn, S(p), a);
+        hipLaunchKernelGGL((k_yfwd<T, EMAX, NTHR, NF, kPsF>), dim3(nb), dim3(NTHR), yfwd_dyn<T>(NF), S(p), a);
     }
     return true;
 }

@@ -70,16 +70,56 @@ __device__ __forceinline__ void block_sum3(double& a, double& b, double& c, doub
     __syncthreads();
 }
 
-// copies the length-N twiddle table exp(2 pi i t / N) into LDS (2 N values);
-// visible after the next barrier
-template <typename T, int NTHR>
-__device__ __forceinline__ T* lds_twiddles(const T* __restrict__ twc, const T* __restrict__ tws, int N) {
+// the length-N twiddle table exp(2 pi i t / N) in LDS (2 N values, in the
+// kernel's dynamic LDS)
+template <typename T>
+__device__ __forceinline__ T* lds_twiddle_ptr() {
     extern __shared__ __align__(16) unsigned char dyn_lds[];
-    T* twl = reinterpret_cast<T*>(dyn_lds);
+    return reinterpret_cast<T*>(dyn_lds);
+}
+
+// copies the twiddle table into LDS; visible after the next barrier.  The
+// compile-time-length kernels call this after issuing their first field
+// loads, so that the table's round trip overlaps theirs.
+template <typename T, int NTHR>
+__device__ __forceinline__ void stage_twiddles(T* twl, const T* __restrict__ twc, const T* __restrict__ tws, int N) {
     for (int t = threadIdx.x; t < N; t += NTHR) {
         twl[t] = twc[t];
         twl[N + t] = tws[t];
     }
+}
+
+// Compile-time length: the table is read into registers first (before the
+// kernel's field loads are issued) and written to LDS after them, so its
+// round trip overlaps theirs instead of preceding it.
+template <typename T, int NTHR, int NF>
+struct TwiddleRegs {
+    static constexpr int IT = (NF + NTHR - 1) / NTHR;
+    T c[IT], s[IT];
+    __device__ __forceinline__ void load(const T* __restrict__ twc, const T* __restrict__ tws) {
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int t = threadIdx.x + r * NTHR;
+            c[r] = (t < NF) ? twc[t] : (T)0;
+            s[r] = (t < NF) ? tws[t] : (T)0;
+        }
+    }
+    __device__ __forceinline__ void store(T* twl) const {
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int t = threadIdx.x + r * NTHR;
+            if (t < NF) {
+                twl[t] = c[r];
+                twl[NF + t] = s[r];
+            }
+        }
+    }
+};
+
+template <typename T, int NTHR>
+__device__ __forceinline__ T* lds_twiddles(const T* __restrict__ twc, const T* __restrict__ tws, int N) {
+    T* twl = lds_twiddle_ptr<T>();
+    stage_twiddles<T, NTHR>(twl, twc, tws, N);
     return twl;
 }
 
@@ -458,8 +498,13 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
         j0 = (int)(row0 - (long)k0 * a.ny);
     }
     const size_t base = (size_t)row0 * N;
-    TO* twl = lds_twiddles<TO, NTHR>(a.twc, a.tws, N);
+    TO* twl = lds_twiddle_ptr<TO>();
+    TwiddleRegs<TO, NTHR, (NF > 0 ? NF : 1)> twr;
+    if constexpr (NF == 0) stage_twiddles<TO, NTHR>(twl, a.twc, a.tws, N);
+    else twr.load(a.twc, a.tws);
     double* __restrict__ out_f = a.out_f;
+    constexpr int PPW = NF > 0 ? NF / NTHR / 2 : 1;
+    TO pw[PPW][4];   // fixed path: post-twiddles (cos, sin) of outputs i and i + 1
     double ss = 0.0, s1 = 0.0, s2 = 0.0, sp = 0.0;
     if constexpr (NF > 0) {
         static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
@@ -474,6 +519,18 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
         static_assert(CPR % 2 == 0, "column pairs");
         PairNb cn[PPR];
         int lp0[PPR], lp1[PPR];
+        // post-twiddles of the outputs this thread stores (m = i, i + 1),
+        // loaded before the field rows
+        // (unconditionally: the tables exist for both boundary kinds, and a
+        // periodic line ignores them)
+#pragma unroll
+        for (int c = 0; c < PPR; ++c) {
+            const int i = 2 * (threadIdx.x + c * NTHR);
+            pw[c][0] = a.dctc[i];
+            pw[c][1] = a.dcts[i];
+            pw[c][2] = a.dctc[i + 1];
+            pw[c][3] = a.dcts[i + 1];
+        }
 #pragma unroll
         for (int c = 0; c < PPR; ++c) {
             const int i = 2 * (threadIdx.x + c * NTHR);
@@ -499,6 +556,7 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
                     }
                 }
             }
+            if (l0 == 0) twr.store(twl);
 #pragma unroll
             for (int lr = 0; lr < RB; ++lr) {
                 const int l = l0 + lr;
@@ -582,13 +640,7 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
             const int mm0 = (m0 == 0) ? 0 : NF - m0, mm1 = NF - m1;
             const int l0 = li(0, m0, SP), lm0 = li(0, mm0, SP), l1 = li(0, m1, SP), lm1 = li(0, mm1, SP);
             const bool lo0 = 2 * m0 <= NF, lo1 = 2 * m1 <= NF;
-            TO wr0 = (TO)1, wi0 = (TO)0, wr1 = (TO)1, wi1 = (TO)0;
-            if (a.bcx == FSEI_BC_WALL) {
-                wr0 = a.dctc[m0];
-                wi0 = -a.dcts[m0];
-                wr1 = a.dctc[m1];
-                wi1 = -a.dcts[m1];
-            }
+            const TO wr0 = pw[c][0], wi0 = -pw[c][1], wr1 = pw[c][2], wi1 = -pw[c][3];
 #pragma unroll
             for (int s = 0; s < NSF; ++s) {
                 VO xa, xb;
@@ -654,7 +706,10 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
     const long nrows = (long)a.ny * a.nz;
     const size_t base = (size_t)row0 * N;
     const T* in = a.in + base;   // not restrict: ACC_KEEP writes this field back (after every read of it)
-    T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
+    T* twl = lds_twiddle_ptr<T>();
+    TwiddleRegs<T, NTHR, (NF > 0 ? NF : 1)> twr;
+    if constexpr (NF == 0) stage_twiddles<T, NTHR>(twl, a.twc, a.tws, N);
+    else twr.load(a.twc, a.tws);
     if constexpr (NF > 0) {
         static_assert(NF % NTHR == 0, "fixed x path: whole columns per thread");
         constexpr int CPR = NF / NTHR;
@@ -667,6 +722,10 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
             const int m = threadIdx.x + c * NTHR;
             const int nm = (m == 0) ? NF / 2 : NF - m;
             const int lm = li(0, m, SP), lnm = li(0, nm, SP);
+            // pre-twiddles, loaded before the rows and unconditionally (a
+            // periodic line ignores them); cos/sin(pi m / 2NF) at NF - m
+            // are sin/cos at m
+            T cm = a.dctc[m], sm = a.dcts[m], c0 = a.dctc[NF / 2], s0 = a.dcts[NF / 2];
             T xam[NSF], xanm[NSF], xbm[NSF], xbnm[NSF];
 #pragma unroll
             for (int s = 0; s < NSF; ++s) {
@@ -675,14 +734,10 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
                 xbm[s] = in[(2 * s + 1) * NF + m];
                 xbnm[s] = in[(2 * s + 1) * NF + nm];
             }
-            // cos/sin(pi m / 2NF) at NF - m are sin/cos at m
-            T cm = (T)1, sm = (T)0, cn = (T)1, sn = (T)0;
-            if (a.bcx == FSEI_BC_WALL) {
-                cm = a.dctc[m];
-                sm = a.dcts[m];
-                cn = (m == 0) ? a.dctc[NF / 2] : sm;
-                sn = (m == 0) ? a.dcts[NF / 2] : cm;
-            }
+            // (not used before the rows are requested)
+            asm volatile("" : "+v"(cm), "+v"(sm), "+v"(c0), "+v"(s0));
+            const T cn = (m == 0) ? c0 : sm, sn = (m == 0) ? s0 : cm;
+            if (c == 0) twr.store(twl);
 #pragma unroll
             for (int s = 0; s < NSF; ++s) {
                 const T pa = (m == 0) ? xanm[s] : xam[s], pb = (m == 0) ? xbnm[s] : xbm[s];
@@ -720,9 +775,32 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
             }
         }
     }
+    TP* __restrict__ out = a.out + base;
+    // fixed path, accumulating epilogues: the values the result is added to
+    // (the iterate, or the FP32 field) are loaded before the transform and
+    // arrive while it runs
+    constexpr bool ACCF = NF > 0 && (EPI == EPI_ACC || EPI == EPI_ADDF || EPI == EPI_ACC_KEEP);
+    constexpr int NLA = ACCF ? 2 * NSF : 1, PPA = ACCF ? NF / NTHR / 2 : 1;
+    using VPA = typename Vec2T<TP>::type;
+    VPA old[NLA][PPA];
+    if constexpr (ACCF) {
+        const float* __restrict__ add = (EPI == EPI_ADDF) ? a.add32 + base : nullptr;
+#pragma unroll
+        for (int l = 0; l < NLA; ++l)
+#pragma unroll
+            for (int c = 0; c < PPA; ++c) {
+                const int o = l * NF + 2 * (threadIdx.x + c * NTHR);
+                if constexpr (EPI == EPI_ADDF) {
+                    const float2 q = *reinterpret_cast<const float2*>(add + o);
+                    old[l][c].x = (TP)q.x;
+                    old[l][c].y = (TP)q.y;
+                } else {
+                    old[l][c] = *reinterpret_cast<const VPA*>(out + o);
+                }
+            }
+    }
     __syncthreads();
     fft_lds<T, EMAX, NTHR, 1, NF>(sre, sim, N, nseq, a.fp, twl, twl + N);
-    TP* __restrict__ out = a.out + base;
     if constexpr (NF > 0) {
         // outputs i, i + 1 (i even) of every line, read and written as pairs
         using VT = typename Vec2T<T>::type;
@@ -736,24 +814,15 @@ __global__ __launch_bounds__(NTHR) void k_xinv(XInvArgs<T, TP> a) {
             ln0[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
             ln1[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i + 1, NF) : i + 1, SP);
         }
-        if constexpr (EPI == EPI_ACC || EPI == EPI_ADDF || EPI == EPI_ACC_KEEP) {
-            VP old[NL][PPR];
-            const float* __restrict__ add = (EPI == EPI_ADDF) ? a.add32 + base : nullptr;
+        if constexpr (ACCF) {
+            static_assert(NLA == NL && PPA == PPR, "prefetched epilogue values");
             const TP msub = a.vsum ? (TP)(a.vsum[0] * a.vscale) : (TP)0;
 #pragma unroll
             for (int l = 0; l < NL; ++l)
 #pragma unroll
                 for (int c = 0; c < PPR; ++c) {
-                    const int o = l * NF + 2 * (threadIdx.x + c * NTHR);
-                    if constexpr (EPI == EPI_ADDF) {
-                        const float2 q = *reinterpret_cast<const float2*>(add + o);
-                        old[l][c].x = (TP)q.x - msub;
-                        old[l][c].y = (TP)q.y - msub;
-                    } else {
-                        old[l][c] = *reinterpret_cast<const VP*>(out + o);
-                        old[l][c].x -= msub;
-                        old[l][c].y -= msub;
-                    }
+                    old[l][c].x -= msub;
+                    old[l][c].y -= msub;
                 }
 #pragma unroll
             for (int l = 0; l < NL; ++l)
@@ -1014,7 +1083,23 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
     const int tile = blockIdx.x - k * a.ntile;
     const int i0 = tile * TX;
     T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
-    T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
+    // Fixed path: the post-twiddles cos, sin (pi m / 2NF) of the output rows
+    // are read before the tile, unconditionally (the tables exist for both
+    // boundary kinds; a periodic line ignores them): a table load between
+    // the stores would make every store wait for the previous one.  FP64
+    // keeps them in registers and its FFT twiddles' round trip overlaps the
+    // tile loads; FP32 tiles, whose second workgroup per CU allows no extra
+    // registers (1024 threads, at most 64 VGPRs), stage both tables in LDS
+    // first (post-twiddles at 2 NF and 3 NF; the launcher sizes the dynamic
+    // LDS).
+    constexpr bool TL = NF > 0 && sizeof(T) == 4;
+    T* twl = lds_twiddle_ptr<T>();
+    TwiddleRegs<T, NTHR, ((NF > 0 && !TL) ? NF : 1)> twr;
+    if constexpr (NF == 0 || TL) stage_twiddles<T, NTHR>(twl, a.twc, a.tws, N);
+    if constexpr (TL) stage_twiddles<T, NTHR>(twl + 2 * NF, a.dctc, a.dcts, NF);
+    if constexpr (NF > 0 && !TL) twr.load(a.twc, a.tws);
+    constexpr int YP = (NF > 0 && !TL) ? NF / (NTHR / (NSF > 0 ? NSF : 1)) : 1;
+    T wr[YP], wi[YP];
     if constexpr (NF > 0) {
         // lane: column pair s (= sequence s), rows jr + r * RPP
         using V2 = typename Vec2T<T>::type;
@@ -1022,9 +1107,24 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
         static_assert(NTHR % NSF == 0 && NF % RPP == 0 && RPP % 2 == 0, "fixed y tile");
         const int s = threadIdx.x % NSF, jr = threadIdx.x / NSF;
         const unsigned lo = (unsigned)(jr * nx + 2 * s);
+        if constexpr (!TL) {
+#pragma unroll
+            for (int r = 0; r < NPASS; ++r) {
+                const int m = jr + r * RPP;
+                wr[r] = a.dctc[m];
+                wi[r] = a.dcts[m];
+            }
+        }
         V2 val[NPASS];
 #pragma unroll
         for (int r = 0; r < NPASS; ++r) val[r] = *reinterpret_cast<const V2*>(d + (size_t)(r * RPP) * nx + lo);
+        // keep the post-twiddles in registers from here on (the compiler
+        // would otherwise reload each next to its use, one wait per row)
+        if constexpr (!TL) {
+#pragma unroll
+            for (int r = 0; r < NPASS; ++r) asm volatile("" : "+v"(wr[r]), "+v"(wi[r]));
+            twr.store(twl);
+        }
 #pragma unroll
         for (int r = 0; r < NPASS; ++r) {
             const int j = jr + r * RPP;
@@ -1066,13 +1166,10 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
             const int m = mr + r * RPP;
             const int mm = (m == 0) ? 0 : NF - m;
             const int om = s * SP + li<PS>(0, m, SP), omm = s * SP + li<PS>(0, mm, SP);
-            T wr = (T)1, wi = (T)0;
-            if (a.bcy == FSEI_BC_WALL) {
-                wr = a.dctc[m];
-                wi = -a.dcts[m];
-            }
             V2 res;
-            post_fwd_v<T>(a.bcy, 2 * m <= NF, sre[om], sim[om], sre[omm], sim[omm], wr, wi, res.x, res.y);
+            const T cr = TL ? twl[2 * NF + m] : wr[TL ? 0 : r];
+            const T sr = TL ? twl[3 * NF + m] : wi[TL ? 0 : r];
+            post_fwd_v<T>(a.bcy, 2 * m <= NF, sre[om], sim[om], sre[omm], sim[omm], cr, -sr, res.x, res.y);
             *reinterpret_cast<V2*>(d + (size_t)(r * RPP) * nx + lo) = res;
         }
     } else {
@@ -1106,7 +1203,10 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
     const int tile = blockIdx.x - k * a.ntile;
     const int i0 = tile * TX;
     T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
-    T* twl = lds_twiddles<T, NTHR>(a.twc, a.tws, N);
+    T* twl = lds_twiddle_ptr<T>();
+    TwiddleRegs<T, NTHR, (NF > 0 ? NF : 1)> twr;
+    if constexpr (NF == 0) stage_twiddles<T, NTHR>(twl, a.twc, a.tws, N);
+    else twr.load(a.twc, a.tws);
     if constexpr (NF > 0) {
         using V2 = typename Vec2T<T>::type;
         constexpr int RPP = NTHR / NSF, NPASS = NF / RPP;
@@ -1118,6 +1218,17 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
         // of those use only their own row)
         constexpr int NH = NPASS / 2;
         static_assert(NPASS % 2 == 0, "paired rows");
+        // pre-twiddles cos/sin(pi m / 2NF) of rows m, loaded before the data
+        // and unconditionally (a periodic line ignores them; at NF - m they
+        // are sin/cos at m; m = 0 pairs with NF/2)
+        T c[NH], sn[NH];
+#pragma unroll
+        for (int r = 0; r < NH; ++r) {
+            const int m = mr + r * RPP;
+            c[r] = a.dctc[m];
+            sn[r] = a.dcts[m];
+        }
+        const T c0 = a.dctc[NF / 2], s0 = a.dcts[NF / 2];
         V2 A[NH], B[NH];
 #pragma unroll
         for (int r = 0; r < NH; ++r) {
@@ -1126,21 +1237,15 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
             A[r] = *reinterpret_cast<const V2*>(d + (size_t)m * nx + lo);
             B[r] = *reinterpret_cast<const V2*>(d + (size_t)nm * nx + lo);
         }
+        twr.store(twl);
 #pragma unroll
         for (int r = 0; r < NH; ++r) {
             const int m = mr + r * RPP;
             const int nm = (m == 0) ? NF / 2 : NF - m;
             const V2 Am = (m == 0) ? B[r] : A[r];
-            // cos/sin(pi m / 2NF) at NF - m are sin/cos at m
-            T c = (T)1, sn = (T)0, cp = (T)1, sp = (T)0;
-            if (a.bcy == FSEI_BC_WALL) {
-                c = a.dctc[m];
-                sn = a.dcts[m];
-                cp = (m == 0) ? a.dctc[NF / 2] : sn;
-                sp = (m == 0) ? a.dcts[NF / 2] : c;
-            }
+            const T cp = (m == 0) ? c0 : sn[r], sp = (m == 0) ? s0 : c[r];
             T zr, zi;
-            pre_inv_cs<T>(NF, m, a.bcy, A[r].x, B[r].x, A[r].y, B[r].y, c, sn, zr, zi);
+            pre_inv_cs<T>(NF, m, a.bcy, A[r].x, B[r].x, A[r].y, B[r].y, c[r], sn[r], zr, zi);
             sre[s * SP + li<PS>(0, m, SP)] = zr;
             sim[s * SP + li<PS>(0, m, SP)] = zi;
             pre_inv_cs<T>(NF, nm, a.bcy, B[r].x, Am.x, B[r].y, Am.y, cp, sp, zr, zi);

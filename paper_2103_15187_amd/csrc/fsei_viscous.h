@@ -59,6 +59,29 @@ __device__ __forceinline__ void visc_load_tables(const double* __restrict__ tab,
     for (int e = threadIdx.x; e < E; e += NT) st[e] = tab[e];
 }
 
+// The same in two steps: every table value of the thread is requested at
+// once (load), and written to LDS once the caller has issued its field
+// loads (store), so that one round trip covers both.
+template <int L, int NT>
+struct ViscTabRegs {
+    static constexpr int E = visc_tab_elems(L), IT = (E + NT - 1) / NT;
+    double v[IT];
+    __device__ __forceinline__ void load(const double* __restrict__ tab) {
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int e = threadIdx.x + r * NT;
+            v[r] = tab[(e < E) ? e : E - 1];
+        }
+    }
+    __device__ __forceinline__ void store(double* __restrict__ st) const {
+#pragma unroll
+        for (int r = 0; r < IT; ++r) {
+            const int e = threadIdx.x + r * NT;
+            if (e < E) st[e] = v[r];
+        }
+    }
+};
+
 // Solve the chunks F[h][0..L-1] of M lines held by this lane (chunk p of
 // lines owned by lane column `ln`); TXL lanes per chunk row of the
 // workgroup, lane index me = p * TXL + ln.  `sc` holds 2 * M * NT scan slots,
@@ -218,7 +241,8 @@ __global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided(ViscArgs a) {
     __shared__ double st[visc_tab_elems(L)];
     __shared__ double sc[2 * M * NT];
     __shared__ double sx[2 * M * TXL];
-    visc_load_tables<L, NT>(a.tab, st);
+    ViscTabRegs<L, NT> tr;
+    tr.load(a.tab);
     const int ln = threadIdx.x % TXL, p = threadIdx.x / TXL;
     const int q0 = (blockIdx.x * TXL + ln) * M;
     const int s0 = p * L;
@@ -226,24 +250,33 @@ __global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided(ViscArgs a) {
     const bool any = q0 < a.ncol;
     double* __restrict__ base = a.data + (size_t)blockIdx.y * a.bstride + (any ? q0 : 0);
     double F[M][L];
+    // Whole vectors for every lane of the workgroup, else element by element
+    // (uniform choice: one load path per row, so the rows' loads are all in
+    // flight together)
+    const bool wg_full = (blockIdx.x + 1) * TXL * M <= a.ncol;
+    if (wg_full) {
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-        const int k = s0 + t;
-        const bool in = k < a.n;
-        if (full) {
+        for (int t = 0; t < L; ++t) {
+            const int k = s0 + t;
             V v = (V)0.0;
-            if (in) v = *reinterpret_cast<const V*>(base + (size_t)k * a.rstride);
+            if (k < a.n) v = *reinterpret_cast<const V*>(base + (size_t)k * a.rstride);
             if constexpr (M == 1) {
                 F[0][t] = v;
             } else {
 #pragma unroll
                 for (int h = 0; h < M; ++h) F[h][t] = v[h];
             }
-        } else {
+        }
+    } else {
 #pragma unroll
-            for (int h = 0; h < M; ++h) F[h][t] = (in && q0 + h < a.ncol) ? base[(size_t)k * a.rstride + h] : 0.0;
+        for (int t = 0; t < L; ++t) {
+            const int k = s0 + t;
+#pragma unroll
+            for (int h = 0; h < M; ++h)
+                F[h][t] = (k < a.n && q0 + h < a.ncol) ? base[(size_t)k * a.rstride + h] : 0.0;
         }
     }
+    tr.store(st);
     __syncthreads();   // tables
     visc_core<M, L, TXL, NT>(F, p, ln, a.n, a.cyc, st, sc, sx);
     if (!any) return;
