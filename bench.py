@@ -50,7 +50,7 @@ SLOT_KERNEL = {
                     "resid": "k_resid_pairs<256, 8, true, float, 2>",
                     "resid_norm": "k_resid_pairs<256, 8, false, double, 2>",
                     "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256, 16>",
-                    "grad_resid": "k_grad_resid<256, 16, false>"},
+                    "grad_resid": "k_grad_resid<256, 16, false>", "xinv_grad_resid": "k_xinv_grad_resid<512>"},
     "viscous_fp64": {"visc_x": "k_visc_x<16>", "visc_y": "k_visc_strided<2, 16>",
                      "visc_z": "k_visc_strided<2, 24>"},
     "momentum_fp64": {"momentum_rhs": "k_momentum_rhs_pairs<64, 16, true>"},
@@ -64,7 +64,10 @@ BYTES_PER_CELL = {
     # FP32 (x inverse writes 4 B; the first residual reads it: f 8 + p 4, r 4
     # written; the first correction reads p32 + delta and writes p 8)
     "fp32_refine": {"xfwd": 36, "yfwd": 8, "zsolve": 8, "yinv": 8, "xinv": 8, "resid_xfwd": 20,
-                    "resid": 16, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 16, "grad": 56, "grad_resid": 64},
+                    "resid": 16, "xfwd_r": 8, "resid_norm": 16, "xinv_acc": 16, "grad": 56, "grad_resid": 64,
+                    # first correction + gradient + check in one pass: correction 4, p32 4, f 8 and
+                    # u, v, w 24 read; u, v, w 24 and p 8 written
+                    "xinv_grad_resid": 72},
     # implicit viscous step: every line solve of one component reads and
     # writes the field once (3 components x 3 directions = 144 B/cell)
     # Poisson solves (f read, p written): FP64 and FP32+refine (FP64 input,

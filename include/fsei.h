@@ -264,7 +264,7 @@ fsei_status fsei_plan_reset_timing(fsei_plan* plan);
 /* Read the accumulated timing of kernel slot `slot` (0 <= slot < FSEI_NUM_KERNEL_SLOTS):
  * total milliseconds and launch count (waits for the stream).  name receives
  * a static string naming the slot's kernel. */
-#define FSEI_NUM_KERNEL_SLOTS 21
+#define FSEI_NUM_KERNEL_SLOTS 22
 fsei_status fsei_plan_kernel_time(fsei_plan* plan, int slot, double* total_ms, long* launches,
                                   const char** name);
 

@@ -26,7 +26,7 @@ namespace {
 const char* kSlotNames[FSEI_NUM_KERNEL_SLOTS] = {
     "xfwd", "yfwd", "zsolve", "yinv", "xinv", "grad", "resid_xfwd", "xinv_acc", "norm", "zero_mode",
     "zsolve_fp64_lines", "resid_norm", "resid", "xfwd_r", "grad_resid", "visc_x", "visc_y", "visc_z", "momentum_rhs", "ib_transfer",
-    "xinv_grad"};
+    "xinv_grad", "xinv_grad_resid"};
 constexpr int K_ZLIST = 10;
 constexpr int K_RESNORM = 11;
 constexpr int K_RESID_PAIRS = 12;
@@ -38,6 +38,7 @@ constexpr int K_VISC_Z = 17;
 constexpr int K_MOM_RHS = 18;
 constexpr int K_IB = 19;
 constexpr int K_XINV_GRAD = 20;
+constexpr int K_XINV_GRAD_RESID = 21;
 
 struct PendingEv {
     hipEvent_t a, b;
@@ -266,6 +267,59 @@ void launch_xinv_grad(fsei_plan* p, const double* in, double* pout, double* u, d
 // and for FP32 also the DCT post-twiddles
 template <typename T>
 size_t yfwd_dyn(int nf) { return (sizeof(T) == 4 ? 4 : 2) * (size_t)nf * sizeof(T); }
+
+// first refinement correction fused with the gradient and the convergence
+// check (FP32 correction, FP64 p): nx of a compiled length, whole 8-row
+// tiles, every field 16-byte aligned; returns the number of partials written
+bool xgr_ok(const fsei_plan* p, const void* in, const void* p32, const void* p64, const void* f, const void* u,
+            const void* v, const void* w) {
+    return (p->nx == 512 || p->nx == 768) && p->ny % kXgRows == 0 && aligned16(in) && aligned16(p32) &&
+           aligned16(p64) && aligned16(f) && aligned16(u) && aligned16(v) && aligned16(w);
+}
+
+long launch_xinv_grad_resid(fsei_plan* p, const float* in, const float* p32, const double* vsum, double* p64,
+                            double* u, double* v, double* w, const double* f, double dt) {
+    XInvGradResArgs a{};
+    a.ny = p->ny;
+    a.nz = p->nz;
+    a.bcx = p->bcx;
+    a.bcy = p->bcy;
+    a.kc = kXgPlanes;
+    a.in = in;
+    a.p32 = p32;
+    a.vsum = vsum;
+    a.vscale = 1.0 / ((double)p->nx * (double)p->ny * p->lz);
+    a.p = p64;
+    a.u = u;
+    a.v = v;
+    a.w = w;
+    a.cx = -dt / p->dx;
+    a.cy = -dt / p->dy;
+    a.sw = -dt;
+    a.bk = tab<double>(p, T_INV_H);
+    a.gk = tab<double>(p, T_INV_H);
+    a.f = f;
+    a.idx2 = 1.0 / (p->dx * p->dx);
+    a.idy2 = 1.0 / (p->dy * p->dy);
+    a.za = tab<double>(p, T_ZA);
+    a.zc = tab<double>(p, T_ZC);
+    a.scal = scalars(p);
+    a.partials = partials(p);
+    a.twc = tab<float>(p, T_TWX_C);
+    a.tws = tab<float>(p, T_TWX_S);
+    a.dctc = tab<float>(p, T_DCTX_C);
+    a.dcts = tab<float>(p, T_DCTX_S);
+    const int nchunk = (p->nz + a.kc - 1) / a.kc;
+    const long nb = (long)(p->ny / kXgRows) * nchunk;
+    Timed t(p, K_XINV_GRAD_RESID);
+    if (p->nx == 768)
+        hipLaunchKernelGGL((k_xinv_grad_resid<768>), dim3((unsigned)nb), dim3(xg_threads<768>()),
+                           2 * 768 * sizeof(float), S(p), a);
+    else
+        hipLaunchKernelGGL((k_xinv_grad_resid<512>), dim3((unsigned)nb), dim3(xg_threads<512>()),
+                           2 * 512 * sizeof(float), S(p), a);
+    return nb;
+}
 
 template <typename T, int EMAX, int NTHR>
 void launch_y_cfg(fsei_plan* p, YArgs<T> a, bool inverse) {
@@ -955,9 +1009,17 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         launch_z<float>(p, w32, 0, false);
         launch_y<float>(p, w32, true);
         const double* vsum = (it == 0) ? vsum0 : nullptr;
+        bool checked = false;   // the gradient and the residual partials of this iterate are done
         if (p_in_32) {
-            // p64 = (p32 - its V-mean) + delta
-            launch_xinv<float, double, EPI_ADDF>(p, w32, p64, K_XINV_ACC, p32, nullptr, vsum);
+            // p64 = (p32 - its V-mean) + delta; with a projection, in the pass
+            // that also applies the gradient of p64 and takes its residual
+            if (fuse && xgr_ok(p, w32, p32, p64, f64, g->u, g->v, g->w)) {
+                nres = launch_xinv_grad_resid(p, w32, p32, vsum, p64, g->u, g->v, g->w, f64, g->dt);
+                g->applied = true;
+                checked = true;
+            } else {
+                launch_xinv<float, double, EPI_ADDF>(p, w32, p64, K_XINV_ACC, p32, nullptr, vsum);
+            }
             p_in_32 = false;
         } else if (fuse && g->applied) {
             // p64 += delta, and delta itself kept (in w32) for its gradient
@@ -970,7 +1032,8 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         if (p->rtol > 0.0) {
             // convergence check of the corrected iterate: norm only, no
             // transform; for a projection fused with the gradient correction
-            if (fuse) {
+            if (checked) {
+            } else if (fuse) {
                 nres = g->applied ? launch_grad_resid<true>(p, g->u, g->v, g->w, f64, p64, w32, g->dt)
                                   : launch_grad_resid<false>(p, g->u, g->v, g->w, f64, p64, nullptr, g->dt);
                 g->applied = true;

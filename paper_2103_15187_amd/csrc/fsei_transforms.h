@@ -1055,6 +1055,246 @@ __global__ __launch_bounds__(xg_threads<NF>()) void k_xinv_grad(XInvGradArgs a) 
 }
 
 // ---------------------------------------------------------------------------
+// The first correction of the FP32 + FP64 refinement fused with the gradient
+// correction and the convergence check (one pass instead of the x inverse
+// with the ADDF epilogue followed by the gradient + residual kernel):
+//     delta = FP32 inverse x transform of the y-inverted correction,
+//     p = (p32 - m) + delta        in FP64 (m: V-mean of the first solve),
+//     u += cx (p_i - p_{i-1}),  v += cy (p_j - p_{j-1}),
+//     w += sw (bk_k p_k - gk_k p_{k-1})        (wall faces written 0),
+//     r = (f - mean) - L p,  per-workgroup partials of sum r^2 and sum r,
+// p written once.  The marching of k_xinv_grad, with 10 rows per plane
+// (halo rows j0-1 and j0+8, both needed by the Laplacian) as 5 complex FP32
+// sequences.  The residual of plane k needs p of plane k+1: its part
+// without that term is kept in registers and completed one step later (the
+// chunk's march takes one plane beyond its end when there is one).
+// Every p is formed from p32 and delta exactly as the ADDF epilogue forms it.
+// ---------------------------------------------------------------------------
+struct XInvGradResArgs {
+    int ny, nz, bcx, bcy, kc;
+    const float* in;        // y-inverted correction (transform space in x), FP32
+    const float* p32;       // first solve
+    const double* vsum;     // vsum[0] * vscale is subtracted from p32
+    double vscale;
+    double* p;              // pressure out (FP64)
+    double* u;
+    double* v;
+    double* w;
+    double cx, cy, sw;
+    const double* bk;
+    const double* gk;
+    const double* f;        // FP64 right-hand side
+    double idx2, idy2;
+    const double* za;
+    const double* zc;
+    const double* scal;     // scal[0] = removed mean of f
+    double* partials;       // per workgroup: sum r^2, sum r, 0
+    const float* twc;
+    const float* tws;
+    const float* dctc;
+    const float* dcts;
+};
+
+template <int NF>
+__global__ __launch_bounds__(xg_threads<NF>()) void k_xinv_grad_resid(XInvGradResArgs a) {
+    constexpr int NTHR = xg_threads<NF>();
+    constexpr int GR = kXgRows, NSQ = kXgSeq, EMAX = NSQ * NF;
+    static_assert(NTHR >= NF / 2, "a column pair per thread");
+    constexpr int SP = seq_stride(NF);
+    constexpr int GB = 2;   // rows per batch of the gradient phase
+    static_assert(NSQ * SP <= lds_elems(EMAX), "tile fits");
+    static_assert(2 * NSQ == GR + 2, "two halo rows + own rows");
+    static_assert(GR % GB == 0, "whole batches");
+    static_assert(NF / 2 <= 64 * (NTHR / 64), "the column-owning threads are in the waves block_sum3 adds");
+    __shared__ float sre[lds_elems(EMAX)];
+    __shared__ float sim[lds_elems(EMAX)];
+    __shared__ double sred[3 * (NTHR / 64 + 1)];
+    const int ny = a.ny, nz = a.nz;
+    const int ntj = ny / GR;
+    const int b = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int chunk = b / ntj;
+    const int jt = b - chunk * ntj;
+    const int j0 = jt * GR;
+    const int kb = chunk * a.kc;
+    const int ke = (kb + a.kc < nz) ? kb + a.kc : nz;
+    const int kend = (ke < nz) ? ke + 1 : ke;   // one plane beyond the chunk for its last residual
+    const int jh = (j0 > 0) ? j0 - 1 : ny - 1;            // halo rows (wrapped; a y wall never uses them)
+    const int jn = (j0 + GR < ny) ? j0 + GR : 0;
+    const bool wallx = a.bcx == FSEI_BC_WALL, wally = a.bcy == FSEI_BC_WALL;
+    float* twl = lds_twiddles<float, NTHR>(a.twc, a.tws, NF);
+    const bool colt = threadIdx.x < NF / 2;   // owns a column (pair)
+    const int m = colt ? threadIdx.x : 0;
+    const int nm = (m == 0) ? NF / 2 : NF - m;
+    const int lm = li(0, m, SP), lnm = li(0, nm, SP);
+    float cm = 1.0f, sm = 0.0f, cn = 1.0f, sn = 0.0f;
+    if (wallx) {
+        cm = a.dctc[m];
+        sm = a.dcts[m];
+        cn = (m == 0) ? a.dctc[NF / 2] : sm;
+        sn = (m == 0) ? a.dcts[NF / 2] : cm;
+    }
+    // this thread's column pair (i, i + 1) and its x neighbours i - 1, i + 2
+    const int i = 2 * m;
+    const int ixm = (i > 0) ? i - 1 : NF - 1;
+    const int ixp = (i + 2 < NF) ? i + 2 : 0;
+    const bool perx = !wallx, pery = !wally;
+    const bool him = (i > 0) || perx, hip = (i + 2 < NF) || perx;
+    const int q0 = li(0, wallx ? mk_pos(i, NF) : i, SP);
+    const int q1 = li(0, wallx ? mk_pos(i + 1, NF) : i + 1, SP);
+    const int qm = li(0, wallx ? mk_pos(ixm, NF) : ixm, SP);
+    const int qp = li(0, wallx ? mk_pos(ixp, NF) : ixp, SP);
+    const size_t plane = (size_t)NF * ny;
+    const double msub = a.vsum ? a.vsum[0] * a.vscale : 0.0;
+    const double mean = a.scal[0];
+    auto rowj = [&](int r) { return (r == 0) ? jh : ((r <= GR) ? j0 + r - 1 : jn); };
+    // step input: the correction's rows (tile row r = 0: row j0 - 1, 1..8:
+    // own rows, 9: row j0 + 8; sequence s pairs rows 2s and 2s + 1)
+    float xa[NSQ][2], xb[NSQ][2];
+    auto load_in = [&](int k) {
+        const float* __restrict__ in = a.in + (size_t)k * plane;
+#pragma unroll
+        for (int s = 0; s < NSQ; ++s) {
+            const float* pa = in + (size_t)rowj(2 * s) * NF;
+            const float* pb = in + (size_t)rowj(2 * s + 1) * NF;
+            xa[s][0] = pa[m];
+            xa[s][1] = pa[nm];
+            xb[s][0] = pb[m];
+            xb[s][1] = pb[nm];
+        }
+    };
+    auto dl = [&](int r, int q) -> double { return (double)((r & 1) ? sim : sre)[(r >> 1) * SP + q]; };
+    // p of tile row r at the thread's pair, from that row's p32 pair: (p32 - m) + delta, in FP64
+    auto pair_p = [&](int r, float2 q) {
+        return make_double2(((double)q.x - msub) + dl(r, q0), ((double)q.y - msub) + dl(r, q1));
+    };
+    double2 prev[GR];    // p of the plane below, own rows
+    double2 rpart[GR];   // residual of the plane below without its z+1 term
+#pragma unroll
+    for (int l = 0; l < GR; ++l) {
+        prev[l] = make_double2(0.0, 0.0);
+        rpart[l] = make_double2(0.0, 0.0);
+    }
+    double ss = 0.0, s1 = 0.0;
+    int k = (kb > 0) ? kb - 1 : 0;
+    for (; k < kend; ++k) {
+        if (colt) load_in(k);
+#pragma unroll
+        for (int s = 0; s < NSQ && colt; ++s) {
+            const float pa = (m == 0) ? xa[s][1] : xa[s][0], pb = (m == 0) ? xb[s][1] : xb[s][0];
+            float zr, zi;
+            pre_inv_cs<float>(NF, m, a.bcx, xa[s][0], xa[s][1], xb[s][0], xb[s][1], cm, sm, zr, zi);
+            sre[s * SP + lm] = zr;
+            sim[s * SP + lm] = zi;
+            pre_inv_cs<float>(NF, nm, a.bcx, xa[s][1], pa, xb[s][1], pb, cn, sn, zr, zi);
+            sre[s * SP + lnm] = zr;
+            sim[s * SP + lnm] = zi;
+        }
+        __syncthreads();
+        fft_lds<float, EMAX, NTHR, 1, NF>(sre, sim, NF, NSQ, FftPlan{}, twl, twl + NF);
+        // uniform over the workgroup: this plane's own rows get the gradient
+        // (grad), complete the residual of the plane below (lag), or only
+        // provide p for the next plane (the chunk's halo plane)
+        const bool grad = k >= kb && k < ke;
+        const bool lag = k - 1 >= kb && k - 1 < ke;
+        if (colt) {
+            const float* __restrict__ p3 = a.p32 + (size_t)k * plane + i;
+            const size_t ro = (size_t)k * plane + (size_t)j0 * NF + i;
+            const double bkk = a.bk[k], gkk = a.gk[k];
+            const double czm = (k > 0) ? a.za[k] : 0.0;
+            const double czl = (k > 0) ? a.zc[k - 1] : 0.0;   // z+1 coefficient of the plane below
+            const bool hzm = k > 0, hzp = k + 1 < nz;
+            double2 pym = make_double2(0.0, 0.0);
+            if (grad) pym = pair_p(0, *reinterpret_cast<const float2*>(p3 + (size_t)jh * NF));
+#pragma unroll
+            for (int l0 = 0; l0 < GR; l0 += GB) {
+                // p32 of tile rows l0+1 .. l0+GB+1 (the last one is the next
+                // batch's first row, needed here for the y Laplacian)
+                float2 q32[GB + 1];
+                float qxm[GB], qxp[GB];
+                double2 uo[GB], vo[GB], wo[GB], fo[GB];
+#pragma unroll
+                for (int t = 0; t <= GB; ++t) {
+                    const int r = l0 + t + 1;
+                    if (t < GB || grad) q32[t] = *reinterpret_cast<const float2*>(p3 + (size_t)rowj(r) * NF);
+                }
+                if (grad) {
+#pragma unroll
+                    for (int t = 0; t < GB; ++t) {
+                        const size_t o = ro + (size_t)(l0 + t) * NF;
+                        const float* pr = a.p32 + (o - i);
+                        qxm[t] = pr[ixm];
+                        qxp[t] = pr[ixp];
+                        uo[t] = *reinterpret_cast<const double2*>(a.u + o);
+                        vo[t] = *reinterpret_cast<const double2*>(a.v + o);
+                        wo[t] = *reinterpret_cast<const double2*>(a.w + o);
+                        fo[t] = *reinterpret_cast<const double2*>(a.f + o);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < GB; ++t) {
+                    const int l = l0 + t, r = l + 1;
+                    const int j = j0 + l;
+                    const double2 pc = pair_p(r, q32[t]);
+                    if (lag) {   // the residual of the plane below, completed with this plane's p
+                        const double r0 = rpart[l].x - czl * (pc.x - prev[l].x);
+                        const double r1 = rpart[l].y - czl * (pc.y - prev[l].y);
+                        ss += r0 * r0 + r1 * r1;
+                        s1 += r0 + r1;
+                    }
+                    if (grad) {
+                        const double2 pyp = pair_p(r + 1, q32[t + 1]);
+                        const double pxm = ((double)qxm[t] - msub) + dl(r, qm);
+                        const double pxp = ((double)qxp[t] - msub) + dl(r, qp);
+                        // gradient correction
+                        double2 un, vn, wn;
+                        un.x = (wallx && i == 0) ? 0.0 : uo[t].x + a.cx * (pc.x - pxm);
+                        un.y = uo[t].y + a.cx * (pc.y - pc.x);
+                        const bool v0 = wally && j == 0;
+                        vn.x = v0 ? 0.0 : vo[t].x + a.cy * (pc.x - pym.x);
+                        vn.y = v0 ? 0.0 : vo[t].y + a.cy * (pc.y - pym.y);
+                        wn.x = (k == 0) ? 0.0 : wo[t].x + a.sw * (bkk * pc.x - gkk * prev[l].x);
+                        wn.y = (k == 0) ? 0.0 : wo[t].y + a.sw * (bkk * pc.y - gkk * prev[l].y);
+                        // residual without the z+1 term
+                        const bool hym = (j > 0) || pery, hyp = (j + 1 < ny) || pery;
+                        const double lx0 = (pc.y - pc.x) + (him ? pxm - pc.x : 0.0);
+                        const double lx1 = (hip ? pxp - pc.y : 0.0) + (pc.x - pc.y);
+                        const double ly0 = (hyp ? pyp.x - pc.x : 0.0) + (hym ? pym.x - pc.x : 0.0);
+                        const double ly1 = (hyp ? pyp.y - pc.y : 0.0) + (hym ? pym.y - pc.y : 0.0);
+                        const double lz0 = hzm ? czm * (prev[l].x - pc.x) : 0.0;
+                        const double lz1 = hzm ? czm * (prev[l].y - pc.y) : 0.0;
+                        const double r0 = (fo[t].x - mean) - (lx0 * a.idx2 + ly0 * a.idy2 + lz0);
+                        const double r1 = (fo[t].y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1);
+                        if (hzp) {
+                            rpart[l] = make_double2(r0, r1);
+                        } else {
+                            ss += r0 * r0 + r1 * r1;
+                            s1 += r0 + r1;
+                        }
+                        const size_t o = ro + (size_t)l * NF;
+                        nt_store2(a.u + o, un);
+                        nt_store2(a.v + o, vn);
+                        nt_store2(a.w + o, wn);
+                        nt_store2(a.p + o, pc);
+                    }
+                    prev[l] = pc;
+                    pym = pc;
+                }
+                // keep the next batch's loads after this batch's stores
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __syncthreads();   // the next step overwrites the tile
+    }
+    double s2 = 0.0;
+    block_sum3<NTHR>(ss, s1, s2, sred);
+    if (threadIdx.x == 0) {
+        a.partials[3 * blockIdx.x] = ss;
+        a.partials[3 * blockIdx.x + 1] = s1;
+        a.partials[3 * blockIdx.x + 2] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // y transforms, in place, on tiles of TX = 2*nseq adjacent x-columns of one
 // z-plane (each column pair is one complex sequence)
 // ---------------------------------------------------------------------------

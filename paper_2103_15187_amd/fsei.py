@@ -25,7 +25,7 @@ WALL = 1
 PREC_FP64 = 0
 PREC_FP32_REFINE = 1
 PREC_FP32 = 2
-NUM_KERNEL_SLOTS = 21   # FSEI_NUM_KERNEL_SLOTS
+NUM_KERNEL_SLOTS = 22   # FSEI_NUM_KERNEL_SLOTS
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfsei.so")
