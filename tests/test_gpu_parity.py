@@ -315,6 +315,30 @@ def test_project_fp64_fixed_length(dims, bc):
     assert max(errs) <= 1e-12
 
 
+@pytest.mark.parametrize("dims,bc", [d for d in FIXED if d[0][0] == 512 and d[0][1] % 8 == 0])
+def test_refine_projection_fixed_length(dims, bc):
+    """nx = 512: the first correction, the gradient correction and the
+    convergence check run as one pass (several plane chunks with a ragged
+    last one, both halo rows of an 8-row tile wrapping in periodic y).  The
+    residual it reports is the residual of the p it stores."""
+    F = fsei()
+    nx, ny, nz = dims
+    spec = W.small_spec(nx, ny, nz, bc[0], bc[1], lx=4.0, ly=3.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 5 * nx + ny + nz)
+    ru, rv, rw, rp = oracle.project(u, v, w, g, dt=0.8)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, dt=0.8, precision=F.PREC_FP32_REFINE, rtol=1e-10,
+                                       max_iter=6)
+    f = oracle.divergence(u, v, w, g) / 0.8
+    res = oracle.rel_residual(f, gp, g)
+    errs = [rel(a, b) for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp))]
+    print(f"dims={dims} bc={bc} info={info} host residual {res:.3e} errs", errs)
+    assert info["iterations"] >= 1 and info["rel_residual"] <= 1e-10
+    assert abs(info["rel_residual"] - res) <= 0.05 * res
+    assert abs(oracle.vmean(gp, g)) <= 1e-13 * np.abs(gp).max()
+    assert errs[3] <= 1e-10 and max(errs[:3]) <= 1e-9
+
+
 def test_project_fp64_fixed_length_without_p():
     """u, v, w only (no pressure output): the fused x-inverse + gradient then
     writes no p at all."""
