@@ -532,7 +532,11 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
         if (c32 && L <= 24 && p->nx % 4 == 0) {
             a.L = L;
             a.P = P;
-            zv_dispatch<float, float, 4, 16, 512>(p, a, dim3((p->nx / 4 + 15) / 16, p->ny));
+            // 8 lanes x 4 modes (128-B rows) in 256-thread workgroups: two
+            // per CU, one solving while the other loads (11 % faster than 16
+            // lanes in 512 threads, one per CU, at 512 x 512 x 768; the FP64
+            // kernel the other way round, 18 % slower)
+            zv_dispatch<float, float, 4, 8, 256>(p, a, dim3((p->nx / 4 + 7) / 8, p->ny));
         } else if (c32 && L <= 24 && p->nx % 2 == 0) {
             a.L = L;
             a.P = P;
