@@ -313,10 +313,10 @@ long launch_xinv_grad_resid(fsei_plan* p, const float* in, const float* p32, con
     const long nb = (long)(p->ny / kXgRows) * nchunk;
     Timed t(p, K_XINV_GRAD_RESID);
     if (p->nx == 768)
-        hipLaunchKernelGGL((k_xinv_grad_resid<768>), dim3((unsigned)nb), dim3(xg_threads<768>()),
+        hipLaunchKernelGGL((k_xinv_grad_resid<768>), dim3((unsigned)nb), dim3(xgr_threads<768>()),
                            2 * 768 * sizeof(float), S(p), a);
     else
-        hipLaunchKernelGGL((k_xinv_grad_resid<512>), dim3((unsigned)nb), dim3(xg_threads<512>()),
+        hipLaunchKernelGGL((k_xinv_grad_resid<512>), dim3((unsigned)nb), dim3(xgr_threads<512>()),
                            2 * 512 * sizeof(float), S(p), a);
     return nb;
 }

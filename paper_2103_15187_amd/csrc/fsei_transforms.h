@@ -1095,9 +1095,14 @@ struct XInvGradResArgs {
     const float* dcts;
 };
 
+// threads of k_xinv_grad_resid: one per column pair at 512 (two workgroups
+// per CU fit the registers), one per radix-8 butterfly at 768
 template <int NF>
-__global__ __launch_bounds__(xg_threads<NF>()) void k_xinv_grad_resid(XInvGradResArgs a) {
-    constexpr int NTHR = xg_threads<NF>();
+constexpr int xgr_threads() { return NF == 512 ? NF / 2 : xg_threads<NF>(); }
+
+template <int NF>
+__global__ __launch_bounds__(xgr_threads<NF>()) void k_xinv_grad_resid(XInvGradResArgs a) {
+    constexpr int NTHR = xgr_threads<NF>();
     constexpr int GR = kXgRows, NSQ = kXgSeq, EMAX = NSQ * NF;
     static_assert(NTHR >= NF / 2, "a column pair per thread");
     constexpr int SP = seq_stride(NF);
