@@ -1033,14 +1033,21 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
         }
         ++it;
         measured = false;
+        bool transformed = false;   // the next correction's transformed residual is in w32
         if (p->rtol > 0.0) {
-            // convergence check of the corrected iterate: norm only, no
-            // transform; for a projection fused with the gradient correction
+            // convergence check of the corrected iterate: for a projection
+            // fused with the gradient correction; for a solve that may take
+            // another correction, the residual pass of that correction (its
+            // partials are this iterate's norm: r is evaluated once, and the
+            // transform is wasted only on the last iteration); else norm only
             if (checked) {
             } else if (fuse) {
                 nres = g->applied ? launch_grad_resid<true>(p, g->u, g->v, g->w, f64, p64, w32, g->dt)
                                   : launch_grad_resid<false>(p, g->u, g->v, g->w, f64, p64, nullptr, g->dt);
                 g->applied = true;
+            } else if (it < p->max_iter) {
+                resid_pass();
+                transformed = true;
             } else {
                 norm_pass();
             }
@@ -1048,7 +1055,8 @@ fsei_status refine_solve(fsei_plan* p, XFwdArgs<double, float> first, double* p6
             if (st != FSEI_OK) return st;
             if (converged || floor) break;
         }
-        if (it < p->max_iter) resid_pass();   // residual again, transformed for the next correction
+        // residual again, transformed for the next correction
+        if (it < p->max_iter && !transformed) resid_pass();
     }
     if (p_in_32) {
         // no correction ran (max_iter = 0, or the first solve already met
