@@ -407,6 +407,29 @@ def test_fp32_and_refine_fixed_length(dims, bc):
     assert abs(oracle.vmean(gp, g)) <= 1e-13 * np.abs(gp).max() and rel(gp, rp) <= 1e-10
 
 
+@pytest.mark.parametrize("rtol", [1e-10, 1e-13])
+def test_refine_poisson_solve_reports_the_residual_of_its_result(rtol):
+    """Solves take one residual pass per correction: the pass that prepares
+    the next correction also gives the previous iterate's norm.  The reported
+    residual is the one of the returned p (host check), for one correction
+    and for several (rtol 1e-13, stopped at the FP64 floor or after four)."""
+    F = fsei()
+    spec = W.small_spec(64, 48, 96, WALL, PERIODIC, lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    f = W.rng(41).standard_normal(spec.shape)
+    rp = oracle.poisson_solve(f, g)
+    plan = F.Plan.from_spec(spec, precision=F.PREC_FP32_REFINE, rtol=rtol, max_iter=4, accept_floor=True)
+    p, info = plan.poisson_solve(dev(f), info=True)
+    torch.cuda.synchronize()
+    gp = host(p)
+    res = oracle.rel_residual(f, gp, g)
+    print(f"rtol {rtol:.0e} info {info} host residual {res:.3e} p err {rel(gp, rp):.2e}")
+    assert info["iterations"] >= (1 if rtol >= 1e-10 else 2)
+    assert abs(info["rel_residual"] - res) <= 0.05 * res
+    assert res <= max(rtol, 1e-12) or info["floor_reached"]
+    assert rel(gp, rp) <= 1e-10
+
+
 def test_refine_without_corrections_returns_the_fp32_solve():
     """max_iter = 0: the FP32 first solve, widened to FP64; its residual is
     the one the library reports."""
