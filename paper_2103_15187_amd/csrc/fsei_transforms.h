@@ -411,8 +411,10 @@ __device__ __forceinline__ PairNb pair_nb(int i, int N, int bcx) {
     return c;
 }
 
-// x_prologue_row for the two adjacent cells (i, i + 1) of a row, every
-// field read as aligned pairs (the scalar x neighbours aside)
+// The divergence / copy prologue for the two adjacent cells (i, i + 1) of a
+// row, every field read as aligned pairs (the scalar x neighbour aside); the
+// residual prologue of the compile-time-length path is written out in
+// k_xfwd (it carries the iterate's rows down the tile)
 template <typename TI, typename TO, int PRO>
 __device__ __forceinline__ void x_prologue_pair(const XFwdArgs<TI, TO>& a, size_t ro, int k, const RowNb& rn,
                                                 const PairNb& cn, TI& v0, TI& v1) {
@@ -421,25 +423,6 @@ __device__ __forceinline__ void x_prologue_pair(const XFwdArgs<TI, TO>& a, size_
         const double2 f = *reinterpret_cast<const double2*>(a.f + ro + cn.i);
         v0 = (TI)f.x;
         v1 = (TI)f.y;
-    } else if constexpr (PRO == PRO_RESID || PRO == PRO_RESID_F) {
-        const auto* __restrict__ p = resid_iterate<PRO>(a) + ro;
-        const double2 pc = pair_d(p + cn.i);
-        const double pxm = (double)p[cn.im], pxp = (double)p[cn.ip2];
-        const double2 pyp = pair_d(p + rn.yp + cn.i);
-        const double2 pym = pair_d(p + rn.ym + cn.i);
-        const double2 pzp = pair_d(p + rn.zp + cn.i);
-        const double2 pzm = pair_d(p + rn.zm + cn.i);
-        const double2 fc = *reinterpret_cast<const double2*>(a.f + ro + cn.i);
-        const double lx0 = (pc.y - pc.x) + (cn.him ? pxm - pc.x : 0.0);
-        const double lx1 = (cn.hip2 ? pxp - pc.y : 0.0) + (pc.x - pc.y);
-        const double ly0 = (rn.hyp ? pyp.x - pc.x : 0.0) + (rn.hym ? pym.x - pc.x : 0.0);
-        const double ly1 = (rn.hyp ? pyp.y - pc.y : 0.0) + (rn.hym ? pym.y - pc.y : 0.0);
-        const double zc = a.zc[k], za = a.za[k];
-        const double lz0 = (rn.hzp ? zc * (pzp.x - pc.x) : 0.0) + (rn.hzm ? za * (pzm.x - pc.x) : 0.0);
-        const double lz1 = (rn.hzp ? zc * (pzp.y - pc.y) : 0.0) + (rn.hzm ? za * (pzm.y - pc.y) : 0.0);
-        const double mean = a.scal[0];
-        v0 = (TI)((fc.x - mean) - (lx0 * a.idx2 + ly0 * a.idy2 + lz0));
-        v1 = (TI)((fc.y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1));
     } else {
         const TI zero = (TI)0;
         const TI* __restrict__ u = a.u + ro;
@@ -538,22 +521,77 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
             lp0[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i, NF) : i, SP);
             lp1[c] = li(0, (a.bcx == FSEI_BC_WALL) ? mk_pos(i + 1, NF) : i + 1, SP);
         }
+        // residual prologue: the iterate's rows carried down the tile (rows
+        // l - 1 and l in registers, row l + 1 loaded; the tile's first and
+        // last rows take their outer neighbours from row_nb), so a row costs
+        // 6 loads instead of 8; same arithmetic as x_prologue_pair
+        double2 pprev[PPR], pcur[PPR];
+        if constexpr (RES) {
+            const auto* __restrict__ pp = resid_iterate<PRO>(a) + base;
+            const RowNb rn0 = row_nb(k0, j0, NF, a.ny, a.nz, a.bcy);
+#pragma unroll
+            for (int c = 0; c < PPR; ++c) {
+                pcur[c] = pair_d(pp + cn[c].i);
+                pprev[c] = pair_d(pp + rn0.ym + (long)cn[c].i);
+            }
+        }
 #pragma unroll
         for (int l0 = 0; l0 < NL; l0 += RB) {
             TI val0[RB][PPR], val1[RB][PPR];
-#pragma unroll
-            for (int lr = 0; lr < RB; ++lr) {
+            if constexpr (RES) {
                 // the host launches this path only when ny is a multiple of
                 // the rows per tile, so all rows of a tile share plane k0
-                const int l = l0 + lr;
-                const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+                const auto* __restrict__ pp = resid_iterate<PRO>(a) + base;
+                double2 pn[RB][PPR], pzp[RB][PPR], pzm[RB][PPR], fc[RB][PPR];
+                double pxm[RB][PPR], pxp[RB][PPR];
 #pragma unroll
-                for (int c = 0; c < PPR; ++c) {
-                    x_prologue_pair<TI, TO, PRO>(a, base + (size_t)l * NF, k0, rn, cn[c], val0[lr][c], val1[lr][c]);
-                    if constexpr (RES) {
-                        const double2 pc = pair_d(resid_iterate<PRO>(a) + base + (size_t)l * NF + cn[c].i);
-                        sp += pc.x + pc.y;
+                for (int lr = 0; lr < RB; ++lr) {
+                    const int l = l0 + lr;
+                    const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+                    const long ynext = (l + 1 < NL) ? (long)NF : rn.yp;
+#pragma unroll
+                    for (int c = 0; c < PPR; ++c) {
+                        const long ro = (long)l * NF + cn[c].i;
+                        pn[lr][c] = pair_d(pp + ro + ynext);
+                        pzp[lr][c] = pair_d(pp + ro + rn.zp);
+                        pzm[lr][c] = pair_d(pp + ro + rn.zm);
+                        fc[lr][c] = *reinterpret_cast<const double2*>(a.f + base + ro);
+                        pxm[lr][c] = (double)pp[(long)l * NF + cn[c].im];
+                        pxp[lr][c] = (double)pp[(long)l * NF + cn[c].ip2];
                     }
+                }
+                const double zc = a.zc[k0], za = a.za[k0], mean = a.scal[0];
+#pragma unroll
+                for (int lr = 0; lr < RB; ++lr) {
+                    const int l = l0 + lr;
+                    const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+#pragma unroll
+                    for (int c = 0; c < PPR; ++c) {
+                        const double2 pc = pcur[c], pym = pprev[c], pyp = pn[lr][c];
+                        const double lx0 = (pc.y - pc.x) + (cn[c].him ? pxm[lr][c] - pc.x : 0.0);
+                        const double lx1 = (cn[c].hip2 ? pxp[lr][c] - pc.y : 0.0) + (pc.x - pc.y);
+                        const double ly0 = (rn.hyp ? pyp.x - pc.x : 0.0) + (rn.hym ? pym.x - pc.x : 0.0);
+                        const double ly1 = (rn.hyp ? pyp.y - pc.y : 0.0) + (rn.hym ? pym.y - pc.y : 0.0);
+                        const double lz0 = (rn.hzp ? zc * (pzp[lr][c].x - pc.x) : 0.0) +
+                                           (rn.hzm ? za * (pzm[lr][c].x - pc.x) : 0.0);
+                        const double lz1 = (rn.hzp ? zc * (pzp[lr][c].y - pc.y) : 0.0) +
+                                           (rn.hzm ? za * (pzm[lr][c].y - pc.y) : 0.0);
+                        val0[lr][c] = (TI)((fc[lr][c].x - mean) - (lx0 * a.idx2 + ly0 * a.idy2 + lz0));
+                        val1[lr][c] = (TI)((fc[lr][c].y - mean) - (lx1 * a.idx2 + ly1 * a.idy2 + lz1));
+                        sp += pc.x + pc.y;
+                        pprev[c] = pc;
+                        pcur[c] = pyp;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int lr = 0; lr < RB; ++lr) {
+                    const int l = l0 + lr;
+                    const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+#pragma unroll
+                    for (int c = 0; c < PPR; ++c)
+                        x_prologue_pair<TI, TO, PRO>(a, base + (size_t)l * NF, k0, rn, cn[c], val0[lr][c],
+                                                     val1[lr][c]);
                 }
             }
             if (l0 == 0) twr.store(twl);
