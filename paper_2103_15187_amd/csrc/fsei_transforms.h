@@ -526,6 +526,11 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
         // last rows take their outer neighbours from row_nb), so a row costs
         // 6 loads instead of 8; same arithmetic as x_prologue_pair
         double2 pprev[PPR], pcur[PPR];
+        typename Vec2T<TI>::type vcur[PPR];
+        if constexpr (PRO == PRO_DIV || PRO == PRO_DIV_ADJ) {
+#pragma unroll
+            for (int c = 0; c < PPR; ++c) vcur[c] = *reinterpret_cast<const typename Vec2T<TI>::type*>(a.v + base + cn[c].i);
+        }
         if constexpr (RES) {
             const auto* __restrict__ pp = resid_iterate<PRO>(a) + base;
             const RowNb rn0 = row_nb(k0, j0, NF, a.ny, a.nz, a.bcy);
@@ -581,6 +586,57 @@ __global__ __launch_bounds__(NTHR) void k_xfwd(XFwdArgs<TI, TO> a) {
                         sp += pc.x + pc.y;
                         pprev[c] = pc;
                         pcur[c] = pyp;
+                    }
+                }
+            } else if constexpr (PRO == PRO_DIV || PRO == PRO_DIV_ADJ) {
+                // divergence: v carried down the tile like the residual's
+                // iterate (row l + 1 of v is row l's y+1 face), 5 loads per row
+                using V = typename Vec2T<TI>::type;
+                V uc[RB][PPR], vn[RB][PPR], wc[RB][PPR], wh[RB][PPR], gv[RB][PPR];
+                TI uh[RB][PPR];
+#pragma unroll
+                for (int lr = 0; lr < RB; ++lr) {
+                    const int l = l0 + lr;
+                    const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+                    const long ynext = (l + 1 < NL) ? (long)NF : rn.yp;
+#pragma unroll
+                    for (int c = 0; c < PPR; ++c) {
+                        const size_t ro = base + (size_t)l * NF;
+                        uc[lr][c] = *reinterpret_cast<const V*>(a.u + ro + cn[c].i);
+                        uh[lr][c] = a.u[ro + cn[c].ip2];
+                        vn[lr][c] = *reinterpret_cast<const V*>(a.v + (long)(ro + cn[c].i) + ynext);
+                        wc[lr][c] = *reinterpret_cast<const V*>(a.w + ro + cn[c].i);
+                        wh[lr][c] = *reinterpret_cast<const V*>(a.w + (long)(ro + cn[c].i) + rn.zp);
+                        if constexpr (PRO == PRO_DIV_ADJ) {
+                            if (a.gp) gv[lr][c] = *reinterpret_cast<const V*>(a.gp + ro + cn[c].i);
+                        }
+                    }
+                }
+                const TI zk = a.zeta[k0], ek = a.eta[k0], zero = (TI)0;
+#pragma unroll
+                for (int lr = 0; lr < RB; ++lr) {
+                    const int l = l0 + lr;
+                    const RowNb rn = row_nb(k0, j0 + l, NF, a.ny, a.nz, a.bcy);
+#pragma unroll
+                    for (int c = 0; c < PPR; ++c) {
+                        const V vc = vcur[c], vh = vn[lr][c];
+                        TI r0 = (uc[lr][c].y - (cn[c].him ? uc[lr][c].x : zero)) * a.idx +
+                                ((rn.hyp ? vh.x : zero) - (rn.hym ? vc.x : zero)) * a.idy +
+                                (zk * (rn.hzp ? wh[lr][c].x : zero) - ek * (rn.hzm ? wc[lr][c].x : zero));
+                        TI r1 = ((cn[c].hip2 ? uh[lr][c] : zero) - uc[lr][c].y) * a.idx +
+                                ((rn.hyp ? vh.y : zero) - (rn.hym ? vc.y : zero)) * a.idy +
+                                (zk * (rn.hzp ? wh[lr][c].y : zero) - ek * (rn.hzm ? wc[lr][c].y : zero));
+                        r0 *= a.alpha;
+                        r1 *= a.alpha;
+                        if constexpr (PRO == PRO_DIV_ADJ) {
+                            if (a.gp) {
+                                r0 += a.beta * gv[lr][c].x;
+                                r1 += a.beta * gv[lr][c].y;
+                            }
+                        }
+                        val0[lr][c] = r0;
+                        val1[lr][c] = r1;
+                        vcur[c] = vh;
                     }
                 }
             } else {
