@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 BCS = [(WALL, WALL), (PERIODIC, WALL), (WALL, PERIODIC), (PERIODIC, PERIODIC)]
-DIMS = [(8, 6, 5), (24, 18, 20), (27, 9, 33), (2, 3, 4), (64, 48, 40)]
+DIMS = [(8, 6, 5), (24, 18, 20), (27, 9, 33), (2, 3, 4), (64, 48, 40), (256, 32, 9), (128, 48, 7)]
 
 
 def fsei():
