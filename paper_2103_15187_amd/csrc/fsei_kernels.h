@@ -259,8 +259,8 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
         tc[k] = in ? a.zc[k] : (TC)0;
         tb[k] = in ? a.zb0[k] : (TC)1;   // diagonal b0_k + sigma * tm_k
         tm[k] = in ? (TC)1 : (TC)0;
-        tsi[k] = in ? (a.transposed ? a.scale * a.inv_dz[k] : a.scale) : (TC)0;
-        tso[k] = in ? (a.transposed ? a.dz[k] : (TC)1) : (TC)0;
+        tsi[k] = in ? (a.transposed ? a.scale * a.inv_dz[k] : (TC)1) : (TC)0;
+        tso[k] = in ? (a.transposed ? a.dz[k] : a.scale) : (TC)0;
     }
     const int ln = threadIdx.x % TXLM;
     const int p = threadIdx.x / TXLM;
@@ -299,10 +299,14 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
         for (int h = 0; h < M; ++h) F[h][t] = (TC)v[h];
     }
     __syncthreads();
+    // the forward solve's uniform 1/(nx ny) is applied at the store (one
+    // multiply fewer per value); the transposed solve's 1/dz_k here
+    if (a.transposed) {
 #pragma unroll
-    for (int t = 0; t < L; ++t)
+        for (int t = 0; t < L; ++t)
 #pragma unroll
-        for (int h = 0; h < M; ++h) F[h][t] *= tsi[s0 + t];
+            for (int h = 0; h < M; ++h) F[h][t] *= tsi[s0 + t];
+    }
     // downward sweep of the M lines (interleaved), first-row back
     // substitution accumulated as running sums (see k_zsolve)
     TC cp[M], dp[M], g[M], pi[M], ys[M], gs[M];
