@@ -41,11 +41,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_c3_512x512x768.json")
 # hardware-counter summary is keyed by kernel name)
 SLOT_KERNEL = {
     "fp64": {"xfwd": "k_xfwd<double, double, 1, 2048, 256, 512>", "yfwd": "k_yfwd<double, 4096, 512, 512, 4>",
-             "zsolve": "k_zsolvev<double, double, 2, 16, 24, 512>", "yinv": "k_yinv<double, 4096, 512, 512, 4>",
+             "zsolve": "k_zsolvev_pf<double, double, 2, 16, 24, 512, 12>", "yinv": "k_yinv<double, 4096, 512, 512, 4>",
              "xinv": "k_xinv<double, double, 0, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256, 16>",
              "xinv_grad": "k_xinv_grad<512>"},
     "fp32_refine": {"xfwd": "k_xfwd<double, float, 1, 2048, 256, 512>", "yfwd": "k_yfwd<float, 8192, 1024, 512, 6>",
-                    "zsolve": "k_zsolvev<float, float, 4, 16, 24, 512>", "yinv": "k_yinv<float, 8192, 1024, 512, 4>",
+                    "zsolve": "k_zsolvev_pf<float, float, 4, 16, 24, 512, 12>", "yinv": "k_yinv<float, 8192, 1024, 512, 4>",
                     "xinv": "k_xinv<float, float, 0, 2048, 256, 512>", "xinv_acc": "k_xinv<float, double, 2, 2048, 256, 512>",
                     "resid": "k_resid_pairs<256, 8, true, float, 2>",
                     "resid_norm": "k_resid_pairs<256, 8, false, double, 2>",

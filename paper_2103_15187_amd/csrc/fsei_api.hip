@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <atomic>
 #include <mutex>
 #include <type_traits>
 #include <vector>
@@ -427,6 +428,20 @@ void launch_y(fsei_plan* p, T* data, bool inverse) {
 
 // chunking of the z lines: P chunks of exactly L rows (L one of the compiled
 // sizes), the last chunk padded with decoupled rows; P <= pmax
+// compute units of the current device (cached per device; 256 if the query fails)
+int cus_of_current_device() {
+    constexpr int kDevs = 64;
+    static std::atomic<int> cus[kDevs];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kDevs) return 256;
+    int n = cus[dev].load(std::memory_order_relaxed);
+    if (n <= 0) {
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 bool choose_chunks(int nz, int pmax, int* L, int* P) {
     static const int sizes[] = {4, 8, 12, 16, 24, 32};
     for (int l : sizes) {
@@ -512,7 +527,22 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
     if constexpr (!F32) {
         ZArgs<double, double> a = zargs<double, double>(p, data, transposed);
         a.sigma_thr = p->sigma_thr;   // the host's threshold, compared in FP64
-        if (c32 && L <= 24 && p->nx % 2 == 0) {
+        if (!transposed && c32 && L == 24 && P == 32 && nz == L * P && p->nx % 32 == 0 && aligned16(data)) {
+            // whole 32-mode tiles of 768 rows: the persistent kernel with the
+            // next tile's first 12 rows of each chunk staged in LDS (0.84 -> 0.66
+            // ms at 512x512x768), one workgroup per CU.  With near-singular
+            // lines, 32 CUs are left to their kernel on the side stream: with
+            // 8 or 16 left it still waited for the whole z solve (0.09 ms in
+            // series); with 32 the z solve takes 0.70 ms and the lines run beside it
+            a.L = L;
+            a.P = P;
+            Timed t(p, K_ZSOLVE);
+            const long ntiles = (long)(p->nx / 32) * p->ny;
+            const int cus = cus_of_current_device();
+            const long want = p->nlist > 0 && cus > 64 ? cus - 32 : cus;
+            const unsigned g = (unsigned)(ntiles < want ? ntiles : want);
+            hipLaunchKernelGGL((k_zsolvev_pf<double, double, 2, 16, 24, 512, 12>), dim3(g), dim3(512), 0, S(p), a);
+        } else if (c32 && L <= 24 && p->nx % 2 == 0) {
             a.L = L;
             a.P = P;
             zv_dispatch<double, double, 2, 16, 512>(p, a, dim3((p->nx / 2 + 15) / 16, p->ny));
@@ -529,7 +559,21 @@ void launch_z(fsei_plan* p, TS* data, int transposed, bool record_mean) {
     } else {
         ZArgs<float, float> a = zargs<float, float>(p, data, transposed);
         a.sigma_thr = p->sigma_thr;   // the host's threshold, compared in FP64
-        if (c32 && L <= 24 && p->nx % 4 == 0) {
+        if (!transposed && c32 && L == 24 && P == 32 && nz == L * P && p->nx % 64 == 0 && aligned16(data)) {
+            // whole 64-mode tiles (256-B rows) of 768 rows: the persistent
+            // kernel, one workgroup per CU, the next tile's first 12 rows of each
+            // chunk staged in LDS (0.39 -> 0.375 ms at 512x512x768 against the
+            // two-workgroup 128-B tiling below); CUs left to the near-singular
+            // lines as in FP64
+            a.L = L;
+            a.P = P;
+            Timed t(p, K_ZSOLVE);
+            const long ntiles = (long)(p->nx / 64) * p->ny;
+            const int cus = cus_of_current_device();
+            const long want = p->nlist > 0 && cus > 64 ? cus - 32 : cus;
+            const unsigned g = (unsigned)(ntiles < want ? ntiles : want);
+            hipLaunchKernelGGL((k_zsolvev_pf<float, float, 4, 16, 24, 512, 12>), dim3(g), dim3(512), 0, S(p), a);
+        } else if (c32 && L <= 24 && p->nx % 4 == 0) {
             a.L = L;
             a.P = P;
             // 8 lanes x 4 modes (128-B rows) in 256-thread workgroups: two

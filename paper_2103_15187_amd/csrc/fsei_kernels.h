@@ -457,6 +457,260 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Persistent form of k_zsolvev for the forward solve on whole tiles (P =
+// NT / TXLM chunks of L rows, nz = P L, nx a multiple of M TXLM, 16-byte
+// vectors), one workgroup per CU: a workgroup walks tiles b, b + gridDim.x,
+// ...; while it solves one tile, the first S rows of every chunk of its next
+// tile come into LDS by direct global-to-LDS loads (no registers held), so
+// the load phase of a tile covers only its last L - S rows and the rest of
+// the tile's bytes arrive while the CU computes.  Each wave reads back only
+// the LDS slots its own loads wrote (slot = wave base + lane), so the buffer
+// needs no barrier, only the wave's own counters.  Same arithmetic, in the
+// same order, as k_zsolvev.
+// ---------------------------------------------------------------------------
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt
+// 11:8): wait until at most n vector-memory operations are outstanding; wait
+// for this wave's LDS operations only
+__device__ constexpr int zpf_wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+__device__ constexpr int zpf_wait_lgkm0() { return 15 | (3 << 14) | (7 << 4); }
+// Workgroup barrier for LDS exchanges while direct loads may still be in
+// flight: this wave's LDS accesses complete, then the barrier, with no memory
+// fence (a fence would wait for the direct loads too); the empty asm keeps
+// the compiler from moving memory accesses across it.
+__device__ __forceinline__ void zpf_sync() {
+    __builtin_amdgcn_s_waitcnt(zpf_wait_lgkm0());
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+template <typename TS, typename TC, int M, int TXLM, int L, int NT, int S>
+__global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
+    using V = typename VecM<TS, M>::type;
+    static_assert(sizeof(V) == 16, "16-byte direct loads");
+    static_assert(S >= 1 && S < L, "prefetched rows");
+    constexpr int P = NT / TXLM;
+    constexpr int NZ = P * L;
+    typedef __attribute__((address_space(3))) void* lds_void;
+    typedef const __attribute__((address_space(1))) void* glb_void;
+    __shared__ TC sh[4][M * NT];
+    __shared__ TC ta[NZ], tc[NZ], tb[NZ], tsi[NZ], tso[NZ];
+    __shared__ V pf[S][NT];
+    const int nx = a.nx;
+    for (int k = threadIdx.x; k < NZ; k += NT) {
+        ta[k] = a.za[k];
+        tc[k] = a.zc[k];
+        tb[k] = a.zb0[k];
+        tsi[k] = a.transposed ? a.scale * a.inv_dz[k] : (TC)1;
+        tso[k] = a.transposed ? a.dz[k] : a.scale;
+    }
+    const int ln = threadIdx.x % TXLM;
+    const int p = threadIdx.x / TXLM;
+    const int s0 = p * L;
+    const int wbase = threadIdx.x & ~63;
+    const int ntx = nx / (M * TXLM);
+    const int ntiles = ntx * a.ny;
+    const size_t strideV = (size_t)nx * a.ny / M;   // in vectors
+    auto coff = [&](int b) -> size_t {              // element offset of the lane's column in tile b
+        const int qy = b / ntx;
+        return (size_t)qy * nx + (size_t)((b - qy * ntx) * TXLM + ln) * M;
+    };
+    auto prefetch = [&](int b) {
+        const V* src = reinterpret_cast<const V*>(a.data + coff(b)) + (size_t)s0 * strideV;
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+            __builtin_amdgcn_global_load_lds((glb_void)(src + (size_t)t * strideV), (lds_void)&pf[t][wbase], 16, 0, 0);
+    };
+    prefetch(blockIdx.x);   // the host launches at most ntiles workgroups
+    __syncthreads();
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const int qy = b / ntx;
+        const int qx0 = (b - qy * ntx) * TXLM * M + ln * M;
+        bool act[M];
+        TC sigma[M];
+        bool anyl = false, alll = true;
+#pragma unroll
+        for (int h = 0; h < M; ++h) {
+            const int qx = qx0 + h;
+            const double s64 = a.lamx64[qx] + a.lamy64[qy];
+            const TC sg = a.lamx[qx] + a.lamy[qy];
+            const bool off = ((qx | qy) == 0) | (fabs(s64) < a.sigma_thr);
+            act[h] = !off;
+            sigma[h] = off ? (TC)-1 : sg;
+            anyl = anyl | act[h];
+            alll = alll & act[h];
+        }
+        // the row stride re-read opaquely each tile, so the compiler rebuilds
+        // the row addresses per tile instead of keeping 24 of them live
+        size_t sv = strideV;
+        asm volatile("" : "+s"(sv));
+        const size_t cof = coff(b);
+        const V* __restrict__ col = reinterpret_cast<const V*>(a.data + cof) + (size_t)s0 * sv;
+        TC F[M][L], Rr[M][L];
+#pragma unroll
+        for (int t = S; t < L; ++t) {
+            const V v = col[(size_t)t * sv];
+#pragma unroll
+            for (int h = 0; h < M; ++h) F[h][t] = (TC)v[h];
+        }
+        // rows 0 .. S-1 from this wave's slots (its direct loads for this
+        // tile were issued before every load above)
+        __builtin_amdgcn_s_waitcnt(zpf_wait_vm(L - S));
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const V v = pf[t][threadIdx.x];
+#pragma unroll
+            for (int h = 0; h < M; ++h) F[h][t] = (TC)v[h];
+        }
+        __builtin_amdgcn_s_waitcnt(zpf_wait_lgkm0());   // buffer read: free for the next tile's rows
+        TC cp[M], dp[M], g[M], pi[M], ys[M], gs[M];
+#pragma unroll
+        for (int h = 0; h < M; ++h) {
+            cp[h] = 0;
+            dp[h] = 0;
+            g[h] = 1;
+            pi[h] = 1;
+            ys[h] = 0;
+            gs[h] = 0;
+        }
+#pragma unroll
+        for (int t = 0; t < L - 1; ++t) {
+            const int k = s0 + t;
+            const TC A = ta[k], C = tc[k], B0 = tb[k];
+#pragma unroll
+            for (int h = 0; h < M; ++h) {
+                const TC r = zrcp(B0 + sigma[h] - A * cp[h]);
+                Rr[h][t] = r;
+                dp[h] = (F[h][t] - A * dp[h]) * r;
+                g[h] = -A * g[h] * r;
+                ys[h] += dp[h] * pi[h];
+                gs[h] += g[h] * pi[h];
+                cp[h] = C * r;
+                pi[h] *= -cp[h];
+            }
+        }
+        // the next tile's first rows: issued once the downward sweep has used
+        // every register row (a wait for a register row behind them would
+        // wait for them too), in flight through the reduction and the sweeps
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            const int nb = b + (int)gridDim.x;
+            prefetch(nb < ntiles ? nb : b);   // the last tile re-reads its own rows (never used)
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const int me = threadIdx.x;
+        TC al[M], be[M], ga[M], ph[M];
+#pragma unroll
+        for (int h = 0; h < M; ++h) {
+            sh[0][M * me + h] = ys[h];
+            sh[1][M * me + h] = gs[h];
+            sh[2][M * me + h] = pi[h];
+        }
+        zpf_sync();
+#pragma unroll
+        for (int h = 0; h < M; ++h) {
+            const int e = s0 + L - 1;
+            const TC Ae = ta[e], Ce = tc[e], Be = tb[e] + sigma[h];
+            al[h] = Ae * g[h];
+            be[h] = Be - Ae * cp[h];
+            ph[h] = F[h][L - 1] - Ae * dp[h];
+            ga[h] = 0;
+            if (p + 1 < P) {
+                const int nb = M * (me + TXLM) + h;
+                be[h] += Ce * sh[1][nb];
+                ga[h] = Ce * sh[2][nb];
+                ph[h] -= Ce * sh[0][nb];
+            }
+        }
+        for (int s = 1; s < P; s <<= 1) {
+            zpf_sync();
+#pragma unroll
+            for (int h = 0; h < M; ++h) {
+                sh[0][M * me + h] = al[h];
+                sh[1][M * me + h] = be[h];
+                sh[2][M * me + h] = ga[h];
+                sh[3][M * me + h] = ph[h];
+            }
+            zpf_sync();
+#pragma unroll
+            for (int h = 0; h < M; ++h) {
+                TC k1 = 0, k2 = 0, alm = 0, gam = 0, phm = 0, alp = 0, gap = 0, php = 0;
+                if (p - s >= 0) {
+                    const int id = M * (me - s * TXLM) + h;
+                    k1 = al[h] * zrcp(sh[1][id]);
+                    alm = sh[0][id];
+                    gam = sh[2][id];
+                    phm = sh[3][id];
+                }
+                if (p + s < P) {
+                    const int id = M * (me + s * TXLM) + h;
+                    k2 = ga[h] * zrcp(sh[1][id]);
+                    alp = sh[0][id];
+                    gap = sh[2][id];
+                    php = sh[3][id];
+                }
+                be[h] = be[h] - k1 * gam - k2 * alp;
+                ph[h] = ph[h] - k1 * phm - k2 * php;
+                al[h] = -k1 * alm;
+                ga[h] = -k2 * gap;
+            }
+        }
+        zpf_sync();
+#pragma unroll
+        for (int h = 0; h < M; ++h) sh[0][M * me + h] = ph[h] * zrcp(be[h]);
+        zpf_sync();
+        TC XR[M], prev[M];
+#pragma unroll
+        for (int h = 0; h < M; ++h) {
+            XR[h] = sh[0][M * me + h];
+            prev[h] = (p > 0) ? sh[0][M * (me - TXLM) + h] : (TC)0;
+        }
+#pragma unroll
+        for (int t = 0; t < L - 1; ++t) {
+            const TC A = ta[s0 + t];
+#pragma unroll
+            for (int h = 0; h < M; ++h) {
+                prev[h] = (F[h][t] - A * prev[h]) * Rr[h][t];
+                F[h][t] = prev[h];
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < M; ++h) F[h][L - 1] = XR[h];
+#pragma unroll
+        for (int t = L - 2; t >= 0; --t) {
+            const TC C = tc[s0 + t];
+#pragma unroll
+            for (int h = 0; h < M; ++h) {
+                XR[h] = F[h][t] - C * Rr[h][t] * XR[h];
+                F[h][t] = XR[h];
+            }
+        }
+        if (anyl) {
+            size_t ooff = cof + (size_t)s0 * strideV * M;
+            asm volatile("" : "+v"(ooff));
+            V* out = reinterpret_cast<V*>(a.data + ooff);
+            TS* outs = a.data + ooff;
+#pragma unroll
+            for (int t = 0; t < L; ++t) {
+                const TC so = tso[s0 + t];
+                if (alll) {
+                    V v;
+#pragma unroll
+                    for (int h = 0; h < M; ++h) v[h] = (TS)(F[h][t] * so);
+                    out[(size_t)t * strideV] = v;
+                } else {
+#pragma unroll
+                    for (int h = 0; h < M; ++h)
+                        if (act[h]) outs[(size_t)t * M * strideV + h] = (TS)(F[h][t] * so);
+                }
+            }
+        }
+        zpf_sync();   // sh is rewritten by the next tile
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // the last direct loads land before the workgroup's LDS is released
+}
+
+// ---------------------------------------------------------------------------
 // Near-singular mode lines: |lambda_x + lambda_y| below the plan's threshold
 // (condition 1 + 4 / (dz_min^2 |sigma|) above 1e4).  One lane per line,
 // sequential Thomas in FP64 with the pivots in row-sum form.  With zero-flux

@@ -87,6 +87,22 @@ def test_project_fp64_tiles_and_ragged(dims, bc):
         assert rel(a, b) <= 1e-12
 
 
+@pytest.mark.parametrize("dims,bc", [((64, 192, 768), (WALL, WALL)), ((32, 288, 768), (PERIODIC, PERIODIC))])
+def test_project_fp64_persistent_z_tiles(dims, bc):
+    """768-row z lines in whole 32-mode tiles take the persistent z kernel
+    (next tile's first rows staged in LDS); 384 and 288 tiles over at most
+    one workgroup per CU, so workgroups solve several tiles in turn."""
+    nx, ny, nz = dims
+    spec = W.small_spec(nx, ny, nz, bc[0], bc[1], lx=4.0, ly=4.0, lz=6.5, stretch=2.5)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 11)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    gu, gv, gw, gp, _ = run_project(spec, u, v, w)
+    print(f"dims={dims} errs u={rel(gu, ru):.2e} v={rel(gv, rv):.2e} w={rel(gw, rw):.2e} p={rel(gp, rp):.2e}")
+    for a, b in ((gu, ru), (gv, rv), (gw, rw), (gp, rp)):
+        assert rel(a, b) <= 1e-12
+
+
 def test_project_fp64_c1():
     spec = W.CONFIGS["C1"]
     g = grid_of(spec)
@@ -570,6 +586,27 @@ def _check_all_precisions(spec, seed, bar32=2e-5):
     # is the plain FP32 error of p)
     assert abs(oracle.vmean(gp, g)) <= max(1e-13, 10 * 2.0 ** -24 * max(e32)) * np.abs(gp).max()
     assert max(ea) <= bar_adj
+
+
+def test_persistent_z_tiles_fp32_and_refine():
+    """768-row z lines in whole 64-mode tiles, 256 of them, more than the
+    persistent FP32 z kernel has workgroups: plain FP32 and FP32+refine
+    against the FP64 oracle (bars as for the fixed-length shapes, plain FP32
+    at 5e-5 for 768-point lines)."""
+    F = fsei()
+    spec = W.small_spec(64, 256, 768, WALL, PERIODIC, lx=4.0, ly=4.0, lz=6.5, stretch=2.0)
+    g = grid_of(spec)
+    u, v, w = W.random_velocity(spec, 29)
+    ru, rv, rw, rp = oracle.project(u, v, w, g)
+    fu, fv, fw, fp, _ = run_project(spec, u, v, w, precision=F.PREC_FP32)
+    e32 = max(rel(a, b) for a, b in ((fu, ru), (fv, rv), (fw, rw)))
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6)
+    print(f"fp32 velocity err {e32:.2e} refine info {info}")
+    assert e32 <= 5e-5
+    assert info["rel_residual"] <= 1e-10
+    assert oracle.rel_residual(oracle.divergence(u, v, w, g), gp, g) <= 1e-10
+    assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
+    assert abs(oracle.vmean(gp, g)) <= 1e-13 * np.abs(gp).max() and rel(gp, rp) <= 1e-10
 
 
 @pytest.mark.parametrize("dims,bc", L768)
