@@ -52,7 +52,7 @@ SLOT_KERNEL = {
                     "xfwd_r": "k_xfwd<float, float, 4, 2048, 256, 512>", "grad": "k_grad_row2<double, double, 256, 16>",
                     "grad_resid": "k_grad_resid<256, 16, false>", "xinv_grad_resid": "k_xinv_grad_resid<512>"},
     "viscous_fp64": {"visc_x": "k_visc_x<16>", "visc_y": "k_visc_strided<2, 16>",
-                     "visc_z": "k_visc_strided<2, 24>"},
+                     "visc_z": "k_visc_strided_pf<24, 12>"},
     "momentum_fp64": {"momentum_rhs": "k_momentum_rhs_pairs<64, 16, true>"},
 }
 

@@ -468,22 +468,6 @@ __global__ __launch_bounds__(NT) void k_zsolvev(ZArgs<TS, TC> a) {
 // needs no barrier, only the wave's own counters.  Same arithmetic, in the
 // same order, as k_zsolvev.
 // ---------------------------------------------------------------------------
-// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt
-// 11:8): wait until at most n vector-memory operations are outstanding; wait
-// for this wave's LDS operations only
-__device__ constexpr int zpf_wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
-__device__ constexpr int zpf_wait_lgkm0() { return 15 | (3 << 14) | (7 << 4); }
-// Workgroup barrier for LDS exchanges while direct loads may still be in
-// flight: this wave's LDS accesses complete, then the barrier, with no memory
-// fence (a fence would wait for the direct loads too); the empty asm keeps
-// the compiler from moving memory accesses across it.
-__device__ __forceinline__ void zpf_sync() {
-    __builtin_amdgcn_s_waitcnt(zpf_wait_lgkm0());
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
 template <typename TS, typename TC, int M, int TXLM, int L, int NT, int S>
 __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
     using V = typename VecM<TS, M>::type;
@@ -555,14 +539,14 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
         }
         // rows 0 .. S-1 from this wave's slots (its direct loads for this
         // tile were issued before every load above)
-        __builtin_amdgcn_s_waitcnt(zpf_wait_vm(L - S));
+        __builtin_amdgcn_s_waitcnt(imm_wait_vm(L - S));
 #pragma unroll
         for (int t = 0; t < S; ++t) {
             const V v = pf[t][threadIdx.x];
 #pragma unroll
             for (int h = 0; h < M; ++h) F[h][t] = (TC)v[h];
         }
-        __builtin_amdgcn_s_waitcnt(zpf_wait_lgkm0());   // buffer read: free for the next tile's rows
+        __builtin_amdgcn_s_waitcnt(imm_wait_lgkm0());   // buffer read: free for the next tile's rows
         TC cp[M], dp[M], g[M], pi[M], ys[M], gs[M];
 #pragma unroll
         for (int h = 0; h < M; ++h) {
@@ -606,7 +590,7 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
             sh[1][M * me + h] = gs[h];
             sh[2][M * me + h] = pi[h];
         }
-        zpf_sync();
+        sync_lds_nofence();
 #pragma unroll
         for (int h = 0; h < M; ++h) {
             const int e = s0 + L - 1;
@@ -623,7 +607,7 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
             }
         }
         for (int s = 1; s < P; s <<= 1) {
-            zpf_sync();
+            sync_lds_nofence();
 #pragma unroll
             for (int h = 0; h < M; ++h) {
                 sh[0][M * me + h] = al[h];
@@ -631,7 +615,7 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
                 sh[2][M * me + h] = ga[h];
                 sh[3][M * me + h] = ph[h];
             }
-            zpf_sync();
+            sync_lds_nofence();
 #pragma unroll
             for (int h = 0; h < M; ++h) {
                 TC k1 = 0, k2 = 0, alm = 0, gam = 0, phm = 0, alp = 0, gap = 0, php = 0;
@@ -655,10 +639,10 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
                 ga[h] = -k2 * gap;
             }
         }
-        zpf_sync();
+        sync_lds_nofence();
 #pragma unroll
         for (int h = 0; h < M; ++h) sh[0][M * me + h] = ph[h] * zrcp(be[h]);
-        zpf_sync();
+        sync_lds_nofence();
         TC XR[M], prev[M];
 #pragma unroll
         for (int h = 0; h < M; ++h) {
@@ -705,7 +689,7 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
                 }
             }
         }
-        zpf_sync();   // sh is rewritten by the next tile
+        sync_lds_nofence();   // sh is rewritten by the next tile
     }
     __builtin_amdgcn_s_waitcnt(0);   // the last direct loads land before the workgroup's LDS is released
 }

@@ -282,6 +282,22 @@ __host__ __device__ constexpr bool y_fixed_ok(int emax, int nthr, int nf, int ps
 template <typename T>
 constexpr int yfwd_pad() { return sizeof(T) == 4 ? 6 : kPadShift; }
 
+// s_waitcnt immediates (vmcnt in bits 3:0 and 15:14, expcnt 6:4, lgkmcnt
+// 11:8): wait until at most n vector-memory operations of this wave are
+// outstanding; wait for this wave's LDS operations only
+__device__ constexpr int imm_wait_vm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+__device__ constexpr int imm_wait_lgkm0() { return 15 | (3 << 14) | (7 << 4); }
+// Workgroup barrier for LDS exchanges while direct global-to-LDS loads may
+// still be in flight: this wave's LDS accesses complete, then the barrier,
+// with no memory fence (a fence would wait for the direct loads too); the
+// empty asm keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void sync_lds_nofence() {
+    __builtin_amdgcn_s_waitcnt(imm_wait_lgkm0());
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // two adjacent values of a field as one vector access
 template <typename T>
 struct Vec2T;

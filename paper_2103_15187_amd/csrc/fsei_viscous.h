@@ -88,11 +88,22 @@ struct ViscTabRegs {
 // Solve the chunks F[h][0..L-1] of M lines held by this lane (chunk p of
 // lines owned by lane column `ln`); TXL lanes per chunk row of the
 // workgroup, lane index me = p * TXL + ln.  `sc` holds 2 * M * NT scan slots,
-// `sx` 2 * M * TXL slots for the periodic correction.  Contains
-// __syncthreads(): every lane of the workgroup must call it.
-template <int M, int L, int TXL, int NT>
+// `sx` 2 * M * TXL slots for the periodic correction.  Contains workgroup
+// barriers (every lane of the workgroup must call it): fenced ones, or with
+// NOFENCE LDS-only ones for callers with direct global-to-LDS loads in
+// flight.  `after_fwd()` runs once the forward substitution has used every
+// row of F (a no-op for most callers).
+struct ViscNoHook {
+    __device__ void operator()() const {}
+};
+template <int M, int L, int TXL, int NT, bool NOFENCE = false, class Hook = ViscNoHook>
 __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int n, int cyc,
-                                          const double* __restrict__ st, double* sc, double* sx) {
+                                          const double* __restrict__ st, double* sc, double* sx,
+                                          Hook after_fwd = Hook()) {
+    auto sync = [] {
+        if constexpr (NOFENCE) sync_lds_nofence();
+        else __syncthreads();
+    };
     constexpr int NP = kViscPmax * L;
     const double* rr = st;
     const double* al = st + NP;
@@ -119,6 +130,7 @@ __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int 
             F[h][t] = d[h];
         }
     }
+    after_fwd();
     // carries of the chunk ends: inclusive scan over the chunks
     double v[M];
 #pragma unroll
@@ -131,7 +143,7 @@ __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int 
         ph ^= 1;
 #pragma unroll
         for (int h = 0; h < M; ++h) b[M * me + h] = v[h];
-        __syncthreads();
+        sync();
         if (p >= s) {
             const double m = wl[lv * kViscPmax + p];
 #pragma unroll
@@ -143,7 +155,7 @@ __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int 
         ph ^= 1;
 #pragma unroll
         for (int h = 0; h < M; ++h) b[M * me + h] = v[h];
-        __syncthreads();
+        sync();
         double dprev[M];
 #pragma unroll
         for (int h = 0; h < M; ++h) dprev[h] = (p > 0) ? b[M * (me - TXL) + h] : 0.0;
@@ -176,7 +188,7 @@ __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int 
         ph ^= 1;
 #pragma unroll
         for (int h = 0; h < M; ++h) b[M * me + h] = v[h];
-        __syncthreads();
+        sync();
         if (p + s < kViscPmax) {
             const double m = vl[lv * kViscPmax + p];
 #pragma unroll
@@ -188,7 +200,7 @@ __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int 
         ph ^= 1;
 #pragma unroll
         for (int h = 0; h < M; ++h) b[M * me + h] = v[h];
-        __syncthreads();
+        sync();
         double xnext[M];
 #pragma unroll
         for (int h = 0; h < M; ++h) xnext[h] = (p + 1 < kViscPmax) ? b[M * (me + TXL) + h] : 0.0;
@@ -216,7 +228,7 @@ __device__ __forceinline__ void visc_core(double (&F)[M][L], int p, int ln, int 
                 sx[M * TXL + M * ln + h] = y;
             }
         }
-        __syncthreads();
+        sync();
         double sm[M];
 #pragma unroll
         for (int h = 0; h < M; ++h) sm[h] = sx[M * ln + h] + vq * sx[M * TXL + M * ln + h];
@@ -317,6 +329,90 @@ __global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided(ViscArgs a) {
             }
         }
     }
+}
+
+// Persistent form of k_visc_strided for whole tiles: two columns per lane,
+// 16 lanes, n = kViscPmax L rows, ncol a multiple of 32, one workgroup per
+// CU walking tiles b, b + gridDim.x, ... (tile = (column block, line group)).
+// While a tile is solved, the first S rows of every chunk of the next tile
+// come into LDS by direct global-to-LDS loads (slot = wave base + lane, so a
+// wave reads back only its own slots), issued once the forward substitution
+// has used every register row; the solve's barriers are LDS-only.  Same
+// arithmetic as k_visc_strided.
+template <int L, int S>
+__global__ __launch_bounds__(16 * kViscPmax) void k_visc_strided_pf(ViscArgs a, int ngx, int ntiles) {
+    constexpr int M = 2, TXL = 16, NT = TXL * kViscPmax;
+    using V = typename ViscVec<M>::type;
+    static_assert(sizeof(V) == 16 && S >= 1 && S < L, "16-byte rows, prefetched rows");
+    typedef __attribute__((address_space(3))) void* lds_void;
+    typedef const __attribute__((address_space(1))) void* glb_void;
+    __shared__ double st[visc_tab_elems(L)];
+    __shared__ double sc[2 * M * NT];
+    __shared__ double sx[2 * M * TXL];
+    __shared__ V pf[S][NT];
+    visc_load_tables<L, NT>(a.tab, st);
+    const int ln = threadIdx.x % TXL, p = threadIdx.x / TXL;
+    const int s0 = p * L;
+    const int wbase = threadIdx.x & ~63;
+    // element offset of the lane's first row in tile b
+    auto first_row = [&](int b) -> size_t {
+        const int gy = b / ngx, gx = b - gy * ngx;
+        return (size_t)gy * a.bstride + (size_t)((gx * TXL + ln) * M) + (size_t)s0 * a.rstride;
+    };
+    auto prefetch = [&](int b) {
+        const double* src = a.data + first_row(b);
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+            __builtin_amdgcn_global_load_lds((glb_void)(src + (size_t)t * a.rstride), (lds_void)&pf[t][wbase], 16, 0, 0);
+    };
+    prefetch(blockIdx.x);   // the host launches at most ntiles workgroups
+    __syncthreads();        // tables
+    for (int b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        // the row stride re-read opaquely each tile: row addresses rebuilt per
+        // tile rather than kept live across the loop
+        size_t rs = a.rstride;
+        asm volatile("" : "+s"(rs));
+        const size_t r0 = first_row(b);
+        const double* __restrict__ col = a.data + r0;
+        double F[M][L];
+#pragma unroll
+        for (int t = S; t < L; ++t) {
+            const V v = *reinterpret_cast<const V*>(col + (size_t)t * rs);
+#pragma unroll
+            for (int h = 0; h < M; ++h) F[h][t] = v[h];
+        }
+        // rows 0 .. S-1 from this wave's slots (their direct loads were
+        // issued before every load above)
+        __builtin_amdgcn_s_waitcnt(imm_wait_vm(L - S));
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const V v = pf[t][threadIdx.x];
+#pragma unroll
+            for (int h = 0; h < M; ++h) F[h][t] = v[h];
+        }
+        __builtin_amdgcn_s_waitcnt(imm_wait_lgkm0());   // buffer read: free for the next tile's rows
+        const int nb = b + (int)gridDim.x;
+        visc_core<M, L, TXL, NT, true>(F, p, ln, a.n, a.cyc, st, sc, sx, [&] {
+            __builtin_amdgcn_sched_barrier(0);
+            prefetch(nb < ntiles ? nb : b);   // the last tile re-reads its own rows (never used)
+            __builtin_amdgcn_sched_barrier(0);
+        });
+        size_t off = r0;
+        asm volatile("" : "+v"(off));
+        const bool acc = a.add != nullptr;   // uniform
+        double* __restrict__ out = (acc ? a.add : a.data) + off;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            V v;
+#pragma unroll
+            for (int h = 0; h < M; ++h) v[h] = F[h][t];
+            V* q = reinterpret_cast<V*>(out + (size_t)t * rs);
+            if (acc) v += *q;
+            *q = v;
+        }
+        sync_lds_nofence();   // sc and sx are rewritten by the next tile
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // the last direct loads land before the workgroup's LDS is released
 }
 
 // Contiguous lines (x): tiles of kViscXLines lines staged through LDS

@@ -86,6 +86,30 @@ def test_viscous_solve_add_matches_oracle(bc):
             assert np.abs(host(u) - ref).max() <= 1e-12 * np.abs(ref).max(), (dims, comp)
 
 
+@pytest.mark.parametrize("dims,bc", [((64, 192, 768), (WALL, WALL)), ((32, 768, 6), (PERIODIC, PERIODIC))])
+def test_viscous_768_row_lines_persistent(dims, bc):
+    """768-row z lines (64 x 192 columns: 384 tiles, several per workgroup) and
+    768-row y lines (periodic) take the persistent strided kernel with the
+    next tile's first rows staged in LDS; solve and solve-add."""
+    spec = W.GridSpec(*dims, bc[0], bc[1], 1.3, 0.9, 1.7, 2.0)
+    g = grid_of(spec)
+    F = fsei()
+    plan = F.Plan.from_spec(spec)
+    r = W.rng(97).standard_normal((2,) + spec.shape)
+    beta = 2.0 * spec.dx**2
+    for comp in range(3):
+        print(f"viscous 768 dims={dims} bc={bc} comp={comp}", flush=True)
+        q = dev(r[0])
+        plan.viscous_solve(q, comp, beta)
+        torch.cuda.synchronize()
+        ref = V.viscous_solve(r[0], g, comp, beta)
+        assert np.abs(host(q) - ref).max() <= 1e-12 * np.abs(ref).max(), (dims, comp)
+        rhs, u = dev(r[0]), dev(r[1])
+        plan.viscous_solve_add(rhs, u, comp, beta)
+        torch.cuda.synchronize()
+        assert np.abs(host(u) - (r[1] + ref)).max() <= 1e-12 * np.abs(r[1] + ref).max(), (dims, comp)
+
+
 def test_viscous_tables_follow_beta_and_component():
     """Alternating beta and component rebuild and reuse the tables correctly."""
     spec = W.GridSpec(32, 24, 36, PERIODIC, WALL, 1.0, 1.0, 1.0, 2.2)
