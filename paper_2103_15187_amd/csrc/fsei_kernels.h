@@ -478,15 +478,14 @@ __global__ __launch_bounds__(NT) void k_zsolvev_pf(ZArgs<TS, TC> a) {
     typedef __attribute__((address_space(3))) void* lds_void;
     typedef const __attribute__((address_space(1))) void* glb_void;
     __shared__ TC sh[4][M * NT];
-    __shared__ TC ta[NZ], tc[NZ], tb[NZ], tsi[NZ], tso[NZ];
+    __shared__ TC ta[NZ], tc[NZ], tb[NZ], tso[NZ];
     __shared__ V pf[S][NT];
     const int nx = a.nx;
     for (int k = threadIdx.x; k < NZ; k += NT) {
         ta[k] = a.za[k];
         tc[k] = a.zc[k];
         tb[k] = a.zb0[k];
-        tsi[k] = a.transposed ? a.scale * a.inv_dz[k] : (TC)1;
-        tso[k] = a.transposed ? a.dz[k] : a.scale;
+        tso[k] = a.scale;   // forward solve only: the uniform 1/(nx ny), applied at the store
     }
     const int ln = threadIdx.x % TXLM;
     const int p = threadIdx.x / TXLM;
