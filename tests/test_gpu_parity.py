@@ -588,22 +588,25 @@ def _check_all_precisions(spec, seed, bar32=2e-5):
     assert max(ea) <= bar_adj
 
 
-def test_persistent_z_tiles_fp32_and_refine():
-    """768-row z lines in whole 64-mode tiles, 256 of them, more than the
-    persistent FP32 z kernel has workgroups: plain FP32 and FP32+refine
-    against the FP64 oracle (bars as for the fixed-length shapes, plain FP32
-    at 5e-5 for 768-point lines)."""
+@pytest.mark.parametrize("ny", [256, 96])
+def test_persistent_z_tiles_fp32_and_refine(ny):
+    """768-row z lines in whole 64-mode tiles: 256 of them (more than the
+    persistent FP32 z kernel has workgroups) and 96 (fewer: one tile per
+    workgroup); plain FP32 and FP32+refine against the FP64 oracle (bars as
+    for the fixed-length shapes, plain FP32 at 5e-5 for 768-point lines)."""
     F = fsei()
-    spec = W.small_spec(64, 256, 768, WALL, PERIODIC, lx=4.0, ly=4.0, lz=6.5, stretch=2.0)
+    spec = W.small_spec(64, ny, 768, WALL, PERIODIC, lx=4.0, ly=4.0, lz=6.5, stretch=2.0)
     g = grid_of(spec)
     u, v, w = W.random_velocity(spec, 29)
     ru, rv, rw, rp = oracle.project(u, v, w, g)
     fu, fv, fw, fp, _ = run_project(spec, u, v, w, precision=F.PREC_FP32)
     e32 = max(rel(a, b) for a, b in ((fu, ru), (fv, rv), (fw, rw)))
-    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-10, max_iter=6)
+    # rtol 1e-12: the error of p follows the residual times the condition of
+    # the lowest modes (residual 1.3e-11 left p at 1.1e-10 on the 96-row shape)
+    gu, gv, gw, gp, info = run_project(spec, u, v, w, precision=F.PREC_FP32_REFINE, rtol=1e-12, max_iter=6)
     print(f"fp32 velocity err {e32:.2e} refine info {info}")
     assert e32 <= 5e-5
-    assert info["rel_residual"] <= 1e-10
+    assert info["rel_residual"] <= (1e-10 if info["floor_reached"] else 1e-12)
     assert oracle.rel_residual(oracle.divergence(u, v, w, g), gp, g) <= 1e-10
     assert max(rel(gu, ru), rel(gv, rv), rel(gw, rw)) <= 1e-9
     assert abs(oracle.vmean(gp, g)) <= 1e-13 * np.abs(gp).max() and rel(gp, rp) <= 1e-10
